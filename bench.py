@@ -1,0 +1,135 @@
+"""Benchmark: 2D crossed supersonic jets, 14-moment maximum-entropy system, 2048 x 2048 cells.
+
+One step = one full SSP-RK2 time step of the whole hot path on every cell (boundary fill,
+primitive recovery, common-limiter MUSCL, sigma-limited closure, approximate wave speeds,
+HLL, BGK source, update, CFL reduction).  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+The workload: unit square, two Maxwellian jets (width 0.1, centred at y = 0.35 and 0.65,
++-30 degrees, Mach 3, rho = 1, T = 1) entering through the left wall into a background at
+rho = 1e-3, T = 1; transmissive elsewhere; Kn = 0.1 through a local BGK collision time;
+MUSCL-minmod, HLL, SSP-RK2, CFL 0.4, sigma_lim = 1e-4.  Inputs are synthetic (the problem
+definition itself; no dataset).
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 2048
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell and stage launch: stage 1 reads U^n and writes U*
+# (2 x 112 B), stage 2 reads U* and U^n and writes U^{n+1} (3 x 112 B)
+BYTES_PER_CELL_STAGE = {1: 224.0, 2: 336.0}
+
+
+def jets_kwargs(n):
+    return dict(system=14, dim=2, nx=n, ny=n, order=2, integrator='ssprk2', flux='hll',
+                limiter='minmod', cfl=0.4, sigma_lim=1e-4,
+                bc=('jet', 'transmissive', 'transmissive', 'transmissive'),
+                jets=[(0.35, 0.1, 30.0), (0.65, 0.1, -30.0)], jet_mach=3.0, jet_rho=1.0,
+                jet_T=1.0)
+
+
+def cpu_baseline(n=128, steps=5):
+    """The oracle, as it stands, on a bounded sample of the same workload (n x n cells of
+    a developed crossed-jets field, `steps` SSP-RK2 steps) on the host cores."""
+    import numpy as np
+    from paper_2401_15233_amd import inputs
+    from oracle import scheme as sc, moments as mo
+    kw = jets_kwargs(n)
+    s = sc.Setup(system=14, dim=2, nx=n, ny=n, order=2, integrator='ssprk2', cfl=0.4,
+                 bc=kw['bc'], jets=kw['jets'])
+    U = mo.prim_to_cons14(inputs.crossed_jets_developed(n, n, seed=0))
+    tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    sc.run(U, s, tau, nsteps=steps)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return {'value': n * n * steps / wall, 'unit': 'cell-updates/s',
+            'cores': max(1, round(cpu / wall)), 'kind': 'oracle',
+            'sample': f'{n}x{n} developed crossed-jets field, {steps} SSP-RK2 steps, FP64 NumPy, '
+                      f'{wall:.1f} s wall'}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=2000)
+    ap.add_argument('--warmup', type=int, default=3)
+    ap.add_argument('--n', type=int, default=N)
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
+        print('bench.py runs on exactly one GPU: the solver has no multi-GPU path (the '
+              'halo-exchange design is described in DESIGN.md); use --gpus 1', file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+
+    torch.cuda.set_device(0)
+    n = a.n
+    kw = jets_kwargs(n)
+    tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
+    stream = torch.cuda.current_stream()
+    s = solver.MaxEntSolver(stream=stream, **kw)
+    s.init_state(inputs.crossed_jets_initial(n, n))
+    if a.warmup:
+        s.step(a.warmup, tau_ref=tau)
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    info = s.step(a.steps, tau_ref=tau)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    stage_ms, launches = s.profile()
+    s.close()
+
+    cells = n * n
+    cups = cells * a.steps / (ms / 1e3)
+    avg_stage_ms = stage_ms / max(launches, 1)
+    bytes_per_launch = cells * 0.5 * (BYTES_PER_CELL_STAGE[1] + BYTES_PER_CELL_STAGE[2])
+    achieved = bytes_per_launch / (avg_stage_ms / 1e3) / 1e9
+    out = {
+        'metric': 'cell-updates/s (14-moment 2D crossed jets, FP64)',
+        'value': cups,
+        'unit': 'cell-updates/s',
+        'n_gpus': 1,
+        'steps': a.steps,
+        'warmup': a.warmup,
+        'ms_per_step': ms / a.steps,
+        'higher_is_better': True,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': 'f64',
+        'data': 'synthetic',
+        'config': {'workload': f'2D crossed jets, 14-moment, {n}x{n}, MUSCL-minmod + HLL + '
+                               f'SSP-RK2, CFL 0.4, Kn 0.1', 'cells': cells, 'precision': 'fp64',
+                   'steps_in_workload': 2000},
+        'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms / 1e3) / 1e9,
+        'sim_time_reached': info['t'],
+        'roofline': {'bound': 'hbm', 'achieved': achieved, 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+                     'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
+                     'kernel': 'stage_kernel<Sys14,2,2>', 'avg_launch_ms': avg_stage_ms,
+                     'launches': launches},
+    }
+    if not a.no_cpu_baseline:
+        out['cpu_baseline'] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,169 @@
+/*
+ * maxent.h -- C-ABI of the MI355X solver for the explicit finite-volume step of the
+ * 5-moment (1D1V) and 14-moment (3V) maximum-entropy moment systems with the interpolative
+ * closure (Boccelli, Kaufmann, Magin & McDonald, arXiv 2401.15233).
+ *
+ * One time step (Section 3 of the paper): primitive recovery, interface reconstruction
+ * with one common limiter (Section 3.2), the sigma-limited interpolative closure
+ * (Sections 2.3-2.4, Appendix A), approximate wave speeds (Section 5.1, Appendix B), the
+ * HLL or Rusanov interface flux (Section 3.1), the BGK relaxation source (Sections
+ * 2.3-2.4), ghost-cell boundary conditions (Section 6) and an explicit Runge-Kutta update
+ * with the CFL time step (Sections 3 and 4.3).
+ *
+ * Conventions for every function below
+ *   - extern "C", never throws, never aborts; returns MAXENT_OK (0) or a negative
+ *     maxent_status.  maxent_last_error() then describes the failure.
+ *   - Field arrays are float64, component-major, unpadded: value (v, j, i) at
+ *     src[(v * ny + j) * nx + i], x fastest.  Component orders:
+ *       14 primitives  [rho, u_x, u_y, u_z, P_xx, P_xy, P_xz, P_yy, P_yz, P_zz, q_x, q_y, q_z, R]
+ *       14 conserved   [rho, rho u_i (3), E_ij = rho u_i u_j + P_ij (6, as P), F_i (3), G]
+ *        5 primitives  [rho, u, P, q, r];  5 conserved [rho, rho u, rho u^2 + P, ...]
+ *     with q_i = Q_ijj (twice the fluid heat flux) and R = R_iijj, gas constant 1.
+ *   - Ownership: the library owns all device state (allocated in maxent_create, freed in
+ *     maxent_destroy).  Caller buffers are only accessed during the call.
+ *   - Streams: all device work is ordered on the stream given to maxent_create (NULL =
+ *     the default stream).  A handle is not thread-safe.
+ */
+#ifndef MAXENT_H
+#define MAXENT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAXENT_ABI_VERSION 1
+
+typedef struct maxent_solver maxent_solver;
+
+typedef enum {
+  MAXENT_OK = 0,
+  MAXENT_E_INVAL = -1,         /* bad argument; the solver state is unchanged            */
+  MAXENT_E_NOMEM = -2,         /* device allocation failed                               */
+  MAXENT_E_DEVICE = -3,        /* a HIP runtime call failed                              */
+  MAXENT_E_NONFINITE = -4,     /* a cell centre became non-finite (info.fail_step)       */
+  MAXENT_E_UNREALIZABLE = -5,  /* rho <= 0 or P not positive definite (info.fail_step)   */
+  MAXENT_E_STATE = -6          /* call out of order (e.g. step before init_state)        */
+} maxent_status;
+
+enum { MAXENT_BC_TRANSMISSIVE = 0, MAXENT_BC_PERIODIC = 1, MAXENT_BC_REFLECTIVE = 2,
+       MAXENT_BC_JET = 3 };
+enum { MAXENT_FP64 = 0 };
+enum { MAXENT_MINMOD = 0, MAXENT_VANALBADA = 1 };
+enum { MAXENT_HLL = 0, MAXENT_RUSANOV = 1 };
+enum { MAXENT_FE = 0, MAXENT_SSPRK2 = 1, MAXENT_MIDPOINT = 2 };
+enum { MAXENT_TAU_LOCAL = 0, MAXENT_TAU_CONST = 1 };
+enum { MAXENT_PRIMITIVE = 0, MAXENT_CONSERVED = 1, MAXENT_SIGMA = 2 };
+
+/* Problem definition.
+ *   system        5 (1D1V, requires dim = 1) or 14.
+ *   dim, nx, ny   1 or 2; ny = 1 when dim = 1.  nx, ny >= 4.
+ *   x0..y1        domain; uniform cells dx = (x1-x0)/nx, dy = (y1-y0)/ny.
+ *   bc[4]         XLO, XHI, YLO, YHI boundary kinds (MAXENT_BC_*).  PERIODIC must be set on
+ *                 both sides of an axis.  JET is accepted on XLO only (Section 6): ghost
+ *                 cells of rows whose centre y lies in [yc - w/2, yc + w/2] of a jet hold
+ *                 the jet Maxwellian, other rows are transmissive.
+ *   jets          up to 4 (centre y, width, angle in degrees from +x toward +y).
+ *   jet_mach, jet_rho, jet_T   the jet Maxwellian: |u| = M sqrt(5/3 T), P = rho T I,
+ *                 q = 0, R = 15 p^2 / rho.
+ *   tau_mode      LOCAL: tau = tau_ref (rho_ref/rho) sqrt(T_ref/T) at each cell centre, the
+ *                 scaling of tau = (n sigma v_th)^-1 of Section 4; CONST: tau = tau_ref.   */
+typedef struct {
+  int system;
+  int dim;
+  int nx, ny;
+  double x0, x1, y0, y1;
+  int bc[4];
+  int n_jets;
+  double jet_yc[4], jet_width[4], jet_angle_deg[4];
+  double jet_mach, jet_rho, jet_T;
+  int tau_mode;
+  double rho_ref, T_ref;
+} maxent_problem;
+
+/* Numerics.
+ *   precision     MAXENT_FP64.
+ *   order         1 (first order, cell states at faces) or 2 (MUSCL on primitives with one
+ *                 common, most stringent limiter factor, Section 3.2).
+ *   limiter       MINMOD or VANALBADA (the paper's choice).
+ *   flux          HLL or RUSANOV (Section 3.1).
+ *   integrator    FE, SSPRK2 (Heun) or MIDPOINT (Section 3).
+ *   cfl           Courant number; dt = cfl dx / max Lambda (1D), cfl / max(Lambda_x/dx +
+ *                 Lambda_y/dy) (2D), Lambda = max |lambda_min|, |lambda_max| at cell centres.
+ *   sigma_lim     lower bound of the parabolic-mapping parameter (Appendix A), e.g. 1e-4.
+ *   k_ws          wave-speed inflation factor k >= 1 (Section 5.1).
+ *   positivity_fallback  1: a cell whose reconstructed face states along a direction have
+ *                 rho <= 0 or a non-positive-definite P is reconstructed at first order. */
+typedef struct {
+  int precision;
+  int order;
+  int limiter;
+  int flux;
+  int integrator;
+  double cfl, sigma_lim, k_ws;
+  int positivity_fallback;
+} maxent_numerics;
+
+/* Per-call report of maxent_step. */
+typedef struct {
+  double t;                 /* simulated time after the call                         */
+  double dt_last;           /* last time step taken                                  */
+  long long steps;          /* steps taken since init_state                          */
+  long long n_fallback;     /* positivity fallbacks since init_state                 */
+  int fail_step;            /* first failing step index (1-based), 0 if none         */
+  int fail_code;            /* bit 1: non-finite, bit 2: rho <= 0 / P not SPD        */
+} maxent_info;
+
+/* Allocate a solver.  `stream` is a hipStream_t (NULL for the default stream).
+ * Errors: INVAL for an inconsistent problem/numerics (nothing allocated), NOMEM, DEVICE. */
+int maxent_create(const maxent_problem* problem, const maxent_numerics* numerics,
+                  void* stream, maxent_solver** out);
+
+/* Set the state.  repr = MAXENT_PRIMITIVE or MAXENT_CONSERVED; src is a field array as
+ * described above, on the host (src_on_device = 0) or the device (1).  Primitives are
+ * converted to conserved moments on the device (the time-derivative terms of the moment
+ * equations, Sections 2.3-2.4).  Sets t = t0, resets step and fallback counters and
+ * computes the first CFL rate.  Errors: INVAL (null src, bad repr), UNREALIZABLE (a cell
+ * with rho <= 0 or P not SPD; the state is loaded anyway), DEVICE. */
+int maxent_init_state(maxent_solver* s, int repr, const double* src, int src_on_device,
+                      double t0);
+
+/* Advance n >= 0 steps.
+ *   dt > 0        fixed time step;  dt <= 0: CFL time step from the cell-centre states.
+ *   tau_ref       BGK reference collision time; tau_ref <= 0 switches the source off
+ *                 (collisionless flow).
+ *   t_end > 0     clip the last step so that t does not pass t_end; steps requested after
+ *                 t_end is reached are no-ops.  t_end <= 0: no end time.
+ * Work is enqueued on the solver's stream; the call synchronises once at the end to read
+ * the status word.  On failure (NONFINITE / UNREALIZABLE) info->fail_step names the first
+ * failing step, later steps of the call do nothing, and the state is the one after the
+ * failing step.  info may be NULL. */
+int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, double t_end,
+                maxent_info* info);
+
+/* Copy out a field.  repr = PRIMITIVE or CONSERVED (nv x ny x nx doubles) or SIGMA (the
+ * unlimited parabolic-mapping parameter, ny x nx).  dst is host (dst_on_device = 0) or
+ * device memory owned by the caller.  Synchronises the solver's stream. */
+int maxent_get_moments(maxent_solver* s, int repr, double* dst, int dst_on_device);
+
+/* Number of components (5 or 14), time and step count of a solver. */
+int maxent_num_vars(const maxent_solver* s);
+int maxent_get_info(maxent_solver* s, maxent_info* info);
+
+/* Optional timing of the fused stage kernels: when enabled, every stage-kernel launch of
+ * maxent_step is bracketed by HIP events on the solver's stream and the elapsed times are
+ * accumulated (read at the end of each maxent_step call).  Enabling resets the totals. */
+int maxent_set_profiling(maxent_solver* s, int enable);
+int maxent_get_profile(maxent_solver* s, double* stage_ms_total, long long* stage_launches);
+
+void maxent_destroy(maxent_solver* s);
+
+/* Last error message of this handle (or of the last failed maxent_create when s is NULL).
+ * The pointer stays valid until the next call on the same handle. */
+const char* maxent_last_error(const maxent_solver* s);
+
+int maxent_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAXENT_H */

@@ -1,0 +1,341 @@
+// C-ABI runtime: handle, device buffers, argument validation, step sequencing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/maxent.h"
+#include "mx_internal.hpp"
+
+using mx::DevCtrl;
+
+struct maxent_solver {
+  maxent_problem prob;
+  maxent_numerics num;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int nv = 14;
+  int pitch = 0;
+  long long plane = 0;
+  double* U = nullptr;       // current state (padded SoA)
+  double* Us = nullptr;      // stage / ping-pong buffer
+  double* stage = nullptr;   // unpadded staging for init / get_moments
+  DevCtrl* ctrl = nullptr;
+  DevCtrl* ctrl_host = nullptr;  // pinned read-back
+  bool ready = false;
+  bool rate_valid = false;
+  // optional per-launch timing of the stage kernels with HIP events
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  long long prof_n = 0;
+  std::string err;
+};
+
+static std::string g_create_err;
+
+static int fail(maxent_solver* s, int code, const std::string& msg) {
+  if (s) s->err = msg; else g_create_err = msg;
+  return code;
+}
+
+#define HIP_TRY(s, call)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((s), MAXENT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
+  if (p.system != 5 && p.system != 14) return "system must be 5 or 14";
+  if (p.dim != 1 && p.dim != 2) return "dim must be 1 or 2";
+  if (p.system == 5 && p.dim != 1) return "the 5-moment system is one-dimensional";
+  if (p.nx < 4) return "nx must be >= 4";
+  if (p.dim == 1 && p.ny != 1) return "ny must be 1 when dim = 1";
+  if (p.dim == 2 && p.ny < 4) return "ny must be >= 4";
+  if ((long long)p.nx * p.ny > (1ll << 31)) return "too many cells";
+  if (!(p.x1 > p.x0)) return "x1 must exceed x0";
+  if (p.dim == 2 && !(p.y1 > p.y0)) return "y1 must exceed y0";
+  int nb = p.dim == 2 ? 4 : 2;
+  for (int k = 0; k < nb; ++k)
+    if (p.bc[k] < 0 || p.bc[k] > 3) return "unknown boundary kind";
+  if ((p.bc[0] == MAXENT_BC_PERIODIC) != (p.bc[1] == MAXENT_BC_PERIODIC))
+    return "periodic x needs both x sides periodic";
+  if (p.dim == 2 && ((p.bc[2] == MAXENT_BC_PERIODIC) != (p.bc[3] == MAXENT_BC_PERIODIC)))
+    return "periodic y needs both y sides periodic";
+  for (int k = 1; k < nb; ++k)
+    if (p.bc[k] == MAXENT_BC_JET) return "jet inflow is only allowed on the x-low side";
+  if (p.bc[0] == MAXENT_BC_JET) {
+    if (p.system != 14 || p.dim != 2) return "jet inflow needs the 2D 14-moment system";
+    if (p.n_jets < 1 || p.n_jets > 4) return "n_jets must be 1..4";
+    if (!(p.jet_rho > 0) || !(p.jet_T > 0) || !(p.jet_mach >= 0)) return "bad jet state";
+    for (int k = 0; k < p.n_jets; ++k)
+      if (!(p.jet_width[k] > 0)) return "jet width must be positive";
+  }
+  if (p.tau_mode != MAXENT_TAU_LOCAL && p.tau_mode != MAXENT_TAU_CONST) return "bad tau_mode";
+  if (p.tau_mode == MAXENT_TAU_LOCAL && !(p.rho_ref > 0 && p.T_ref > 0)) return "bad rho_ref/T_ref";
+  if (n.precision != MAXENT_FP64) return "unsupported precision";
+  if (n.order != 1 && n.order != 2) return "order must be 1 or 2";
+  if (n.limiter != MAXENT_MINMOD && n.limiter != MAXENT_VANALBADA) return "bad limiter";
+  if (n.flux != MAXENT_HLL && n.flux != MAXENT_RUSANOV) return "bad flux";
+  if (n.integrator < MAXENT_FE || n.integrator > MAXENT_MIDPOINT) return "bad integrator";
+  if (!(n.cfl > 0 && n.cfl <= 1)) return "cfl must be in (0, 1]";
+  if (!(n.sigma_lim > 0 && n.sigma_lim < 1)) return "sigma_lim must be in (0, 1)";
+  if (!(n.k_ws >= 1)) return "k_ws must be >= 1";
+  return "";
+}
+
+extern "C" int maxent_abi_version(void) { return MAXENT_ABI_VERSION; }
+
+extern "C" const char* maxent_last_error(const maxent_solver* s) {
+  return s ? s->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" int maxent_num_vars(const maxent_solver* s) { return s ? s->nv : 0; }
+
+extern "C" void maxent_destroy(maxent_solver* s) {
+  if (!s) return;
+  if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+  if (s->U) (void)hipFree(s->U);
+  if (s->Us) (void)hipFree(s->Us);
+  if (s->stage) (void)hipFree(s->stage);
+  if (s->ctrl) (void)hipFree(s->ctrl);
+  if (s->ctrl_host) (void)hipHostFree(s->ctrl_host);
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  delete s;
+}
+
+extern "C" int maxent_create(const maxent_problem* problem, const maxent_numerics* numerics,
+                             void* stream, maxent_solver** out) {
+  if (!problem || !numerics || !out) return fail(nullptr, MAXENT_E_INVAL, "null argument");
+  *out = nullptr;
+  std::string why = validate(*problem, *numerics);
+  if (!why.empty()) return fail(nullptr, MAXENT_E_INVAL, why);
+  maxent_solver* s = new (std::nothrow) maxent_solver();
+  if (!s) return fail(nullptr, MAXENT_E_NOMEM, "host allocation failed");
+  s->prob = *problem;
+  s->num = *numerics;
+  if (s->prob.dim == 1) { s->prob.bc[2] = s->prob.bc[3] = MAXENT_BC_TRANSMISSIVE; }
+  s->stream = (hipStream_t)stream;
+  s->nv = problem->system;
+  s->pitch = ((problem->nx + 15) / 16) * 16;   // rows start on 128-byte boundaries
+  s->plane = (long long)problem->ny * s->pitch;
+  size_t field = (size_t)s->nv * s->plane * sizeof(double);
+  size_t flat = (size_t)s->nv * problem->nx * problem->ny * sizeof(double);
+  hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = hipMalloc(&s->U, field);
+  if (e == hipSuccess) e = hipMalloc(&s->Us, field);
+  if (e == hipSuccess) e = hipMalloc(&s->stage, flat);
+  if (e == hipSuccess) e = hipMalloc(&s->ctrl, sizeof(DevCtrl));
+  if (e == hipSuccess) e = hipHostMalloc(&s->ctrl_host, sizeof(DevCtrl));
+  if (e == hipSuccess) e = hipMemsetAsync(s->U, 0, field, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->Us, 0, field, s->stream);
+  if (e == hipSuccess) e = mx::launch_ctrl_reset(s->ctrl, 0.0, s->stream);
+  if (e != hipSuccess) {
+    int code = (e == hipErrorOutOfMemory) ? MAXENT_E_NOMEM : MAXENT_E_DEVICE;
+    std::string m = std::string("allocation failed: ") + hipGetErrorString(e);
+    maxent_destroy(s);
+    return fail(nullptr, code, m);
+  }
+  *out = s;
+  return MAXENT_OK;
+}
+
+static mx::StageParams stage_params(maxent_solver* s, double tau_ref) {
+  mx::StageParams p;
+  std::memset(&p, 0, sizeof(p));
+  const maxent_problem& q = s->prob;
+  p.nx = q.nx; p.ny = q.ny; p.pitch = s->pitch; p.plane = s->plane;
+  p.x0 = q.x0; p.y0 = q.y0;
+  p.dx = (q.x1 - q.x0) / q.nx;
+  p.dy = q.dim == 2 ? (q.y1 - q.y0) / q.ny : 1.0;
+  p.inv_dx = 1.0 / p.dx;
+  p.inv_dy = 1.0 / p.dy;
+  for (int k = 0; k < 4; ++k) p.bc[k] = q.bc[k];
+  p.n_jets = q.bc[0] == MAXENT_BC_JET ? q.n_jets : 0;
+  for (int k = 0; k < 4; ++k) {
+    p.jet_yc[k] = q.jet_yc[k]; p.jet_w[k] = q.jet_width[k]; p.jet_ang[k] = q.jet_angle_deg[k];
+  }
+  p.jet_mach = q.jet_mach; p.jet_rho = q.jet_rho; p.jet_T = q.jet_T;
+  p.use_source = (tau_ref > 0 && std::isfinite(tau_ref)) ? 1 : 0;
+  p.tau_mode = q.tau_mode; p.tau_ref = tau_ref; p.rho_ref = q.rho_ref; p.T_ref = q.T_ref;
+  p.sigma_lim = s->num.sigma_lim; p.kws = s->num.k_ws;
+  p.limiter = s->num.limiter; p.flux = s->num.flux; p.fallback = s->num.positivity_fallback;
+  if (q.dim == 2) { p.ntx = (q.nx + 15) / 16; p.nty = (q.ny + 14) / 15; }
+  else { p.ntx = (q.nx + 62) / 63; p.nty = 1; }
+  p.nblk = p.ntx * p.nty;
+  p.ctrl = s->ctrl;
+  return p;
+}
+
+static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::StageParams& p) {
+  if (!s->prof) return mx::launch_stage(sys, dim, ord, p, s->stream);
+  while (s->ev.size() < s->ev_used + 2) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    s->ev.push_back(e);
+  }
+  hipError_t r = hipEventRecord(s->ev[s->ev_used], s->stream);
+  if (r == hipSuccess) r = mx::launch_stage(sys, dim, ord, p, s->stream);
+  if (r == hipSuccess) r = hipEventRecord(s->ev[s->ev_used + 1], s->stream);
+  s->ev_used += 2;
+  return r;
+}
+
+static hipError_t collect_profile(maxent_solver* s) {
+  for (size_t k = 0; k + 1 < s->ev_used; k += 2) {
+    float ms = 0.f;
+    hipError_t r = hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]);
+    if (r != hipSuccess) return r;
+    s->prof_ms += ms;
+    s->prof_n += 1;
+  }
+  s->ev_used = 0;
+  return hipSuccess;
+}
+
+static hipError_t run_cfl(maxent_solver* s) {
+  mx::CflParams c;
+  c.U = s->U; c.nx = s->prob.nx; c.ny = s->prob.ny; c.pitch = s->pitch; c.plane = s->plane;
+  c.dx = (s->prob.x1 - s->prob.x0) / s->prob.nx;
+  c.dy = s->prob.dim == 2 ? (s->prob.y1 - s->prob.y0) / s->prob.ny : 1.0;
+  c.sigma_lim = s->num.sigma_lim; c.kws = s->num.k_ws; c.ctrl = s->ctrl;
+  return mx::launch_cfl(s->prob.system, s->prob.dim, c, s->stream);
+}
+
+static int read_ctrl(maxent_solver* s) {
+  HIP_TRY(s, hipMemcpyAsync(s->ctrl_host, s->ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return MAXENT_OK;
+}
+
+static void fill_info(maxent_solver* s, maxent_info* info) {
+  if (!info) return;
+  const DevCtrl& c = *s->ctrl_host;
+  info->t = c.t;
+  info->dt_last = c.dt_last;
+  info->steps = c.step;
+  info->n_fallback = c.n_fallback;
+  info->fail_step = (c.fail_step == 0x7fffffff) ? 0 : c.fail_step;
+  info->fail_code = c.status;
+}
+
+extern "C" int maxent_init_state(maxent_solver* s, int repr, const double* src, int src_on_device,
+                                 double t0) {
+  if (!s) return MAXENT_E_INVAL;
+  if (!src) return fail(s, MAXENT_E_INVAL, "null src");
+  if (repr != MAXENT_PRIMITIVE && repr != MAXENT_CONSERVED)
+    return fail(s, MAXENT_E_INVAL, "repr must be PRIMITIVE or CONSERVED");
+  if (!std::isfinite(t0)) return fail(s, MAXENT_E_INVAL, "t0 must be finite");
+  size_t flat = (size_t)s->nv * s->prob.nx * s->prob.ny * sizeof(double);
+  HIP_TRY(s, hipMemcpyAsync(s->stage, src, flat,
+                            src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(s, mx::launch_ctrl_reset(s->ctrl, t0, s->stream));
+  HIP_TRY(s, mx::launch_ingest(s->prob.system, repr, s->stage, s->U, s->prob.nx, s->prob.ny,
+                               s->pitch, s->ctrl, s->stream));
+  HIP_TRY(s, run_cfl(s));
+  int rc = read_ctrl(s);
+  if (rc) return rc;
+  s->ready = true;
+  s->rate_valid = true;
+  int st = s->ctrl_host->status;
+  if (st) {
+    // keep the loaded state but clear the status so that the caller may inspect it
+    HIP_TRY(s, mx::launch_ctrl_reset(s->ctrl, t0, s->stream));
+    HIP_TRY(s, run_cfl(s));
+    s->ready = false;
+    if (st & mx::ST_NONFINITE) return fail(s, MAXENT_E_NONFINITE, "initial state has non-finite values");
+    return fail(s, MAXENT_E_UNREALIZABLE, "initial state has rho <= 0 or a non-SPD pressure tensor");
+  }
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, double t_end,
+                           maxent_info* info) {
+  if (!s) return MAXENT_E_INVAL;
+  if (n < 0) return fail(s, MAXENT_E_INVAL, "n must be >= 0");
+  if (std::isnan(dt) || std::isinf(dt)) return fail(s, MAXENT_E_INVAL, "dt must be finite");
+  if (std::isnan(tau_ref)) return fail(s, MAXENT_E_INVAL, "tau_ref is NaN");
+  if (std::isnan(t_end)) return fail(s, MAXENT_E_INVAL, "t_end is NaN");
+  if (!s->ready) return fail(s, MAXENT_E_STATE, "step before a valid init_state");
+  const bool cfl_mode = !(dt > 0);
+  mx::StageParams p = stage_params(s, tau_ref);
+  const int sys = s->prob.system, dim = s->prob.dim, ord = s->num.order;
+  const double dx = (s->prob.x1 - s->prob.x0) / s->prob.nx;
+  HIP_TRY(s, mx::launch_ctrl_set(s->ctrl, cfl_mode ? 0.0 : dt, t_end > 0 ? t_end : 0.0, s->stream));
+  if (cfl_mode && !s->rate_valid) HIP_TRY(s, run_cfl(s));
+  for (int k = 0; k < n; ++k) {
+    HIP_TRY(s, mx::launch_finalize(s->ctrl, dim, s->num.cfl, dx, s->stream));
+    if (s->num.integrator == MAXENT_FE) {
+      p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
+      p.mode = mx::MODE_EULER; p.cdt = 1.0; p.do_cfl = cfl_mode; p.copy_on_idle = 1;
+      HIP_TRY(s, stage(s, sys, dim, ord, p));
+      // the result lives in Us; swap so that U is always the current state
+      double* tmp = s->U; s->U = s->Us; s->Us = tmp;
+      continue;
+    }
+    p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
+    p.mode = mx::MODE_EULER;
+    p.copy_on_idle = 0;
+    p.cdt = (s->num.integrator == MAXENT_MIDPOINT) ? 0.5 : 1.0;
+    p.do_cfl = 0;
+    HIP_TRY(s, stage(s, sys, dim, ord, p));
+    p.Ub = s->Us; p.Ua = s->U; p.Uout = s->U;
+    p.mode = (s->num.integrator == MAXENT_MIDPOINT) ? mx::MODE_MID2 : mx::MODE_HEUN2;
+    p.cdt = 1.0;
+    p.do_cfl = cfl_mode;
+    HIP_TRY(s, stage(s, sys, dim, ord, p));
+  }
+  int rc = read_ctrl(s);
+  if (rc) return rc;
+  if (s->prof) HIP_TRY(s, collect_profile(s));
+  if (n > 0) s->rate_valid = cfl_mode;  // the last stage reduced the rate of the new state
+  fill_info(s, info);
+  int st = s->ctrl_host->status;
+  if (st & mx::ST_NONFINITE) return fail(s, MAXENT_E_NONFINITE, "non-finite cell state");
+  if (st & mx::ST_UNREALIZABLE) return fail(s, MAXENT_E_UNREALIZABLE, "rho <= 0 or P not SPD at a cell");
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_get_info(maxent_solver* s, maxent_info* info) {
+  if (!s || !info) return MAXENT_E_INVAL;
+  int rc = read_ctrl(s);
+  if (rc) return rc;
+  fill_info(s, info);
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_get_moments(maxent_solver* s, int repr, double* dst, int dst_on_device) {
+  if (!s) return MAXENT_E_INVAL;
+  if (!dst) return fail(s, MAXENT_E_INVAL, "null dst");
+  if (repr != MAXENT_PRIMITIVE && repr != MAXENT_CONSERVED && repr != MAXENT_SIGMA)
+    return fail(s, MAXENT_E_INVAL, "repr must be PRIMITIVE, CONSERVED or SIGMA");
+  size_t cells = (size_t)s->prob.nx * s->prob.ny;
+  size_t bytes = (repr == MAXENT_SIGMA ? 1 : (size_t)s->nv) * cells * sizeof(double);
+  HIP_TRY(s, mx::launch_egress(s->prob.system, repr, s->U, s->stage, s->prob.nx, s->prob.ny,
+                               s->pitch, s->stream));
+  HIP_TRY(s, hipMemcpyAsync(dst, s->stage, bytes,
+                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_set_profiling(maxent_solver* s, int enable) {
+  if (!s) return MAXENT_E_INVAL;
+  s->prof = enable != 0;
+  s->prof_ms = 0.0;
+  s->prof_n = 0;
+  s->ev_used = 0;
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_get_profile(maxent_solver* s, double* stage_ms_total, long long* stage_launches) {
+  if (!s || !stage_ms_total || !stage_launches) return MAXENT_E_INVAL;
+  *stage_ms_total = s->prof_ms;
+  *stage_launches = s->prof_n;
+  return MAXENT_OK;
+}

@@ -1,0 +1,70 @@
+// Internal interface between the C-ABI runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mx {
+
+// Device-resident control block: time step, time and status live on the device so that a
+// sequence of steps needs no host round trip.
+struct DevCtrl {
+  double dt;                     // time step of the current step (0: step is a no-op)
+  double t;                      // time after the current step's update
+  double t_end;                  // > 0: clip to t_end
+  double dt_fixed;               // > 0: fixed time step
+  double dt_last;
+  unsigned long long maxrate;    // bit pattern of the max CFL rate (positive double)
+  long long step;                // steps taken (1-based index of the current step)
+  long long n_fallback;          // positivity fallbacks
+  int status;                    // bit 1 non-finite, bit 2 unrealizable
+  int fail_step;                 // first failing step (0: none)
+};
+
+enum { MODE_EULER = 0, MODE_HEUN2 = 1, MODE_MID2 = 2 };
+enum { ST_NONFINITE = 1, ST_UNREALIZABLE = 2 };
+
+struct StageParams {
+  const double* Ub;        // stage input, read with its neighbourhood
+  const double* Ua;        // U^n for the second-stage combinations (may equal Uout)
+  double* Uout;
+  int nx, ny, pitch;
+  long long plane;         // ny * pitch
+  double x0, y0, dx, dy, inv_dx, inv_dy;
+  int bc[4];
+  int n_jets;
+  double jet_yc[4], jet_w[4], jet_ang[4];
+  double jet_mach, jet_rho, jet_T;
+  int use_source, tau_mode;
+  double tau_ref, rho_ref, T_ref;
+  double sigma_lim, kws;
+  int limiter, flux, fallback;
+  int mode;
+  double cdt;              // stage step = cdt * dt (EULER mode)
+  int do_cfl;
+  int copy_on_idle;        // dt == 0: copy Ub to Uout (forward-Euler ping-pong) instead of skipping
+  int ntx, nty;            // tile grid
+  int nblk;                // real number of tiles
+  DevCtrl* ctrl;
+};
+
+struct CflParams {
+  const double* U;
+  int nx, ny, pitch;
+  long long plane;
+  double dx, dy;
+  double sigma_lim, kws;
+  DevCtrl* ctrl;
+};
+
+// launchers (mx_kernels.hip)
+hipError_t launch_stage(int system, int dim, int order, const StageParams& p, hipStream_t s);
+hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s);
+hipError_t launch_finalize(DevCtrl* c, int dim, double cfl, double dx, hipStream_t s);
+hipError_t launch_ctrl_set(DevCtrl* c, double dt_fixed, double t_end, hipStream_t s);
+hipError_t launch_ctrl_reset(DevCtrl* c, double t0, hipStream_t s);
+// src/dst: unpadded [nv][ny][nx]; U: padded [nv][ny][pitch]
+hipError_t launch_ingest(int system, int repr, const double* src, double* U, int nx, int ny,
+                         int pitch, DevCtrl* c, hipStream_t s);
+hipError_t launch_egress(int system, int repr, const double* U, double* dst, int nx, int ny,
+                         int pitch, hipStream_t s);
+
+}  // namespace mx

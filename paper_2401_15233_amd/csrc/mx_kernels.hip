@@ -1,0 +1,596 @@
+// gfx950 kernels of the finite-volume step (FP64).
+//
+// One fused kernel per Runge-Kutta stage.  A workgroup owns a TX x TY tile of cells and
+//   1. loads the tile plus a G-cell halo of the stage input U (structure of arrays, x
+//      fastest), applying the boundary conditions while loading (ghost cells are never
+//      stored), converts to primitives and keeps them in LDS;
+//   2. computes the common (most stringent) limiter factor of every cell that feeds a face
+//      of the tile (Section 3.2), with the positivity fallback;
+//   3. evaluates every face of the tile once: both reconstructed states, their closure
+//      (Sections 2.3-2.4, Appendix A), wave speeds (Section 5.1), physical fluxes and the
+//      HLL / Rusanov combination (Section 3.1);
+//   4. updates each cell with the flux differences and the BGK source at the cell centre,
+//      writes the result, checks it (non-finite, rho <= 0, P not SPD) and, in the last
+//      stage of a step, reduces the CFL rate of the new state for the next step.
+// The 2D tile is 16 x 15 cells for 256 threads: 255 x-faces and 256 y-faces, one of each
+// per thread.  The 1D tile is 63 cells for one 64-wide wavefront: 64 faces.
+#include "mx_internal.hpp"
+#include "mx_physics.hpp"
+
+namespace mx {
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ boundary mapping
+__device__ __forceinline__ int map_axis(int g, int n, int lo, int hi, int& refl) {
+  if (g < 0) {
+    if (lo == 1) g = g + n * ((-g + n - 1) / n);
+    else if (lo == 2) { g = -g - 1; refl = 1; }
+    else g = 0;
+  } else if (g >= n) {
+    if (hi == 1) g = g % n;
+    else if (hi == 2) { g = 2 * n - 1 - g; refl = 1; }
+    else g = n - 1;
+  }
+  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
+template <class SYS>
+__device__ __forceinline__ void load_prims(const StageParams& p, const double* U, int gi, int gj,
+                                           double* W) {
+  constexpr int NV = SYS::NV;
+  int rx = 0, ry = 0;
+  int si = map_axis(gi, p.nx, p.bc[0], p.bc[1], rx);
+  int sj = map_axis(gj, p.ny, p.bc[2], p.bc[3], ry);
+  double Uc[NV];
+  const double* src = U + (long long)sj * p.pitch + si;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Uc[v] = src[v * p.plane];
+  SYS::cons_to_prim(Uc, W);
+  if (rx) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (SYS::odd(v, 0)) W[v] = -W[v];
+  }
+  if (ry) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (SYS::odd(v, 1)) W[v] = -W[v];
+  }
+  if constexpr (NV == 14) {
+    if (gi < 0 && p.bc[0] == 3) {
+      double yc = p.y0 + ((double)sj + 0.5) * p.dy;
+      for (int k = 0; k < p.n_jets; ++k) {
+        if (yc >= p.jet_yc[k] - 0.5 * p.jet_w[k] && yc <= p.jet_yc[k] + 0.5 * p.jet_w[k]) {
+          double sn, cs;
+          sincospi(p.jet_ang[k] / 180.0, &sn, &cs);
+          double spd = p.jet_mach * sqrt(5.0 / 3.0 * p.jet_T);
+          double pj = p.jet_rho * p.jet_T;
+          W[0] = p.jet_rho;
+          W[1] = spd * cs; W[2] = spd * sn; W[3] = 0.0;
+          W[4] = pj; W[5] = 0.0; W[6] = 0.0; W[7] = pj; W[8] = 0.0; W[9] = pj;
+          W[10] = 0.0; W[11] = 0.0; W[12] = 0.0;
+          W[13] = 15.0 * pj * pj / p.jet_rho;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ limiter
+template <class SYS>
+__device__ __forceinline__ double limiter_factor(const double* Wm, const double* Wc,
+                                                 const double* Wp, int kind) {
+  constexpr int NV = SYS::NV;
+  double sc[NV];
+  SYS::scales(Wc, sc);
+  double phi = 1.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double a = Wc[v] - Wm[v];
+    double b = Wp[v] - Wc[v];
+    double aa = fabs(a), ab = fabs(b);
+    double f;
+    if (aa + ab <= 1e-10 * sc[v]) f = 1.0;
+    else if (a * b <= 0.0) f = 0.0;
+    else if (kind == 0) f = 2.0 * fmin(aa, ab) / (aa + ab);
+    else f = 2.0 * a * b / (a * a + b * b);
+    phi = fmin(phi, f);
+  }
+  return phi;
+}
+
+template <class SYS>
+__device__ __forceinline__ void face_state(const double* Wm, const double* Wc, const double* Wp,
+                                           double phi, double sgn, double* Wf) {
+#pragma unroll
+  for (int v = 0; v < SYS::NV; ++v) {
+    double a = Wc[v] - Wm[v];
+    double b = Wp[v] - Wc[v];
+    double s = phi * (a + b) / 2.0;
+    Wf[v] = Wc[v] + sgn * (s / 2.0);
+  }
+}
+
+// ------------------------------------------------------------------ face flux
+template <class SYS, int D>
+__device__ __forceinline__ void face_flux(const double* WL, const double* WR, const StageParams& p,
+                                          double* Fh) {
+  constexpr int NV = SYS::NV;
+  double UL[NV], FL[NV], UR[NV], FR[NV];
+  double lminL, lmaxL, lminR, lmaxR;
+  SYS::template face_terms<D>(WL, p.sigma_lim, p.kws, UL, FL, lminL, lmaxL);
+  SYS::template face_terms<D>(WR, p.sigma_lim, p.kws, UR, FR, lminR, lmaxR);
+  if (p.flux == 0) {
+    double SL = fmin(lminL, lminR), SR = fmax(lmaxL, lmaxR);
+    if (SL >= 0.0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fh[v] = FL[v];
+    } else if (SR <= 0.0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fh[v] = FR[v];
+    } else {
+      double inv = 1.0 / (SR - SL);
+      double SLR = SL * SR;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fh[v] = (SR * FL[v] - SL * FR[v] + SLR * (UR[v] - UL[v])) * inv;
+    }
+  } else {
+    double am = fmax(fmax(fabs(lminL), fabs(lmaxL)), fmax(fabs(lminR), fabs(lmaxR)));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * am * (UR[v] - UL[v]);
+  }
+}
+
+// ------------------------------------------------------------------ stage kernel
+template <class SYS, int DIM, int ORDER, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
+  constexpr int NV = SYS::NV;
+  constexpr int G = (ORDER == 2) ? 2 : 1;
+  constexpr int LX = TX + 2 * G;
+  constexpr int LY = (DIM == 2) ? TY + 2 * G : 1;
+  constexpr int NL = LX * LY;
+  constexpr int NFX = (TX + 1) * TY;
+  constexpr int NFY = (DIM == 2) ? TX * (TY + 1) : 0;
+  constexpr int NPX = (ORDER == 2) ? (TX + 2) * TY : 1;
+  constexpr int NPY = (ORDER == 2 && DIM == 2) ? TX * (TY + 2) : 1;
+  constexpr int NW = (NV * NL > NV * NFY) ? NV * NL : NV * NFY;
+  static_assert(NFX <= NT || DIM == 1, "one x-face per thread");
+
+  __shared__ double sW[NW];        // primitives of the tile + halo; later the y-face fluxes
+  __shared__ double sFx[NV * NFX];
+  __shared__ double sPx[NPX];
+  __shared__ double sPy[NPY];
+  __shared__ double sRed[NT / 64];
+  __shared__ int sFlag[2];
+
+  // XCD-aware tile order: hardware deals consecutive workgroups round-robin to the 8
+  // XCDs; give each XCD a contiguous band of tiles so halos are shared in its L2.
+  const int nb8 = (p.nblk + 7) / 8;
+  const int b = blockIdx.x;
+  const int tile = (b % 8) * nb8 + b / 8;
+  if (tile >= p.nblk) return;
+  const int i0 = (tile % p.ntx) * TX;
+  const int j0 = (tile / p.ntx) * TY;
+  const int t = threadIdx.x;
+
+  const double dt = p.ctrl->dt;
+  if (!(dt > 0.0)) {  // uniform: time end reached or a failure stopped the run
+    if (p.copy_on_idle && t < TX * TY) {
+      int gi = i0 + t % TX, gj = j0 + t / TX;
+      if (gi < p.nx && gj < p.ny) {
+        long long off = (long long)gj * p.pitch + gi;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) p.Uout[v * p.plane + off] = p.Ub[v * p.plane + off];
+      }
+    }
+    return;
+  }
+  if (t < 2) sFlag[t] = 0;
+
+  // 1. tile + halo -> primitives in LDS
+  for (int c = t; c < NL; c += NT) {
+    int li = c % LX, lj = c / LX;
+    double W[NV];
+    load_prims<SYS>(p, p.Ub, i0 + li - G, (DIM == 2) ? j0 + lj - G : 0, W);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sW[v * NL + c] = W[v];
+  }
+  __syncthreads();
+
+  auto lds = [&](int ti, int tj, double* W) {
+    int c = (DIM == 2) ? (tj + G) * LX + (ti + G) : (ti + G);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) W[v] = sW[v * NL + c];
+  };
+
+  // 2. common limiter factors
+  int nfb = 0;
+  if constexpr (ORDER == 2) {
+    for (int c = t; c < NPX; c += NT) {
+      int ti = c % (TX + 2) - 1, tj = c / (TX + 2);
+      double Wm[NV], Wc[NV], Wp[NV];
+      lds(ti - 1, tj, Wm); lds(ti, tj, Wc); lds(ti + 1, tj, Wp);
+      double phi = limiter_factor<SYS>(Wm, Wc, Wp, p.limiter);
+      if (p.fallback && phi > 0.0) {
+        double Wf[NV];
+        face_state<SYS>(Wm, Wc, Wp, phi, 1.0, Wf);
+        bool ok = SYS::admissible(Wf);
+        face_state<SYS>(Wm, Wc, Wp, phi, -1.0, Wf);
+        ok = ok && SYS::admissible(Wf);
+        if (!ok) {
+          phi = 0.0;
+          if (ti >= 0 && ti < TX && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
+        }
+      }
+      sPx[c] = phi;
+    }
+    if constexpr (DIM == 2) {
+      for (int c = t; c < NPY; c += NT) {
+        int ti = c % TX, tj = c / TX - 1;
+        double Wm[NV], Wc[NV], Wp[NV];
+        lds(ti, tj - 1, Wm); lds(ti, tj, Wc); lds(ti, tj + 1, Wp);
+        double phi = limiter_factor<SYS>(Wm, Wc, Wp, p.limiter);
+        if (p.fallback && phi > 0.0) {
+          double Wf[NV];
+          face_state<SYS>(Wm, Wc, Wp, phi, 1.0, Wf);
+          bool ok = SYS::admissible(Wf);
+          face_state<SYS>(Wm, Wc, Wp, phi, -1.0, Wf);
+          ok = ok && SYS::admissible(Wf);
+          if (!ok) {
+            phi = 0.0;
+            if (tj >= 0 && tj < TY && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
+          }
+        }
+        sPy[c] = phi;
+      }
+    }
+    __syncthreads();
+  }
+
+  // 3a. x faces: face f lies between tile cells (fi-1, fj) and (fi, fj)
+  for (int f = t; f < NFX; f += NT) {
+    int fi = f % (TX + 1), fj = f / (TX + 1);
+    double WL[NV], WR[NV];
+    if constexpr (ORDER == 2) {
+      double A[NV], B[NV], C[NV], D[NV];
+      lds(fi - 2, fj, A); lds(fi - 1, fj, B); lds(fi, fj, C); lds(fi + 1, fj, D);
+      face_state<SYS>(A, B, C, sPx[fj * (TX + 2) + fi], 1.0, WL);
+      face_state<SYS>(B, C, D, sPx[fj * (TX + 2) + fi + 1], -1.0, WR);
+    } else {
+      lds(fi - 1, fj, WL); lds(fi, fj, WR);
+    }
+    double Fh[NV];
+    face_flux<SYS, 0>(WL, WR, p, Fh);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
+  }
+
+  // 3b. y faces: face f lies between tile cells (fi, fj-1) and (fi, fj)
+  double Fy[NV];
+  const bool has_y = (DIM == 2) && (t < NFY);
+  if constexpr (DIM == 2) {
+    static_assert(NFY <= NT, "one y-face per thread");
+    if (has_y) {
+      int fi = t % TX, fj = t / TX;
+      double WL[NV], WR[NV];
+      if constexpr (ORDER == 2) {
+        double A[NV], B[NV], C[NV], D[NV];
+        lds(fi, fj - 2, A); lds(fi, fj - 1, B); lds(fi, fj, C); lds(fi, fj + 1, D);
+        face_state<SYS>(A, B, C, sPy[fj * TX + fi], 1.0, WL);
+        face_state<SYS>(B, C, D, sPy[(fj + 1) * TX + fi], -1.0, WR);
+      } else {
+        lds(fi, fj - 1, WL); lds(fi, fj, WR);
+      }
+      if constexpr (SYS::NV == 14) face_flux<SYS, 1>(WL, WR, p, Fy);
+    }
+  }
+  __syncthreads();
+  if constexpr (DIM == 2) {
+    if (has_y) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sW[v * NFY + t] = Fy[v];
+    }
+    __syncthreads();
+  }
+
+  // 4. update
+  int flag = 0;
+  double rate = 0.0;
+  if (t < TX * TY) {
+    int ci = t % TX, cj = t / TX;
+    int gi = i0 + ci, gj = j0 + cj;
+    if (gi < p.nx && gj < p.ny) {
+      long long off = (long long)gj * p.pitch + gi;
+      double Ub[NV], W[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + off];
+      SYS::cons_to_prim(Ub, W);
+      double Cs[NV];
+      if (p.use_source) {
+        double rho = W[0];
+        double T = SYS::pressure(W) / rho;
+        double tau = (p.tau_mode == 0) ? p.tau_ref * (p.rho_ref / rho) * sqrt(p.T_ref / T) : p.tau_ref;
+        SYS::source(W, 1.0 / tau, Cs);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Cs[v] = 0.0;
+      }
+      double Un[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double L = -(sFx[v * NFX + cj * (TX + 1) + ci + 1] - sFx[v * NFX + cj * (TX + 1) + ci]) * p.inv_dx;
+        if constexpr (DIM == 2)
+          L = L - (sW[v * NFY + (cj + 1) * TX + ci] - sW[v * NFY + cj * TX + ci]) * p.inv_dy;
+        L = L + Cs[v];
+        double o;
+        if (p.mode == MODE_EULER) o = Ub[v] + (p.cdt * dt) * L;
+        else if (p.mode == MODE_HEUN2) o = 0.5 * p.Ua[v * p.plane + off] + 0.5 * (Ub[v] + dt * L);
+        else o = p.Ua[v * p.plane + off] + dt * L;
+        Un[v] = o;
+        p.Uout[v * p.plane + off] = o;
+      }
+      bool fin = true;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fin = fin && isfinite(Un[v]);
+      double Wn[NV];
+      SYS::cons_to_prim(Un, Wn);
+      if (!fin) flag |= ST_NONFINITE;
+      else if (!SYS::admissible(Wn)) flag |= ST_UNREALIZABLE;
+      if (p.do_cfl && flag == 0) {
+        if constexpr (DIM == 1) {
+          rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws);
+        } else {
+          rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws) / p.dx +
+                 SYS::template cell_lambda<1>(Wn, p.sigma_lim, p.kws) / p.dy;
+        }
+      }
+    }
+  }
+  // block reductions: status, fallback count, CFL rate
+  flag = wave_or(flag);
+  nfb = wave_sum(nfb);
+  const int lane = t & 63, wid = t >> 6;
+  if (lane == 0) {
+    if (flag) atomicOr(&sFlag[0], flag);
+    if (nfb) atomicAdd(&sFlag[1], nfb);
+  }
+  if (p.do_cfl) {
+    rate = wave_max(rate);
+    if (lane == 0) sRed[wid] = rate;
+  }
+  __syncthreads();
+  if (t == 0) {
+    if (sFlag[0]) {
+      atomicOr(&p.ctrl->status, sFlag[0]);
+      atomicMin(&p.ctrl->fail_step, (int)p.ctrl->step);
+    }
+    if (sFlag[1]) atomicAdd((unsigned long long*)&p.ctrl->n_fallback, (unsigned long long)sFlag[1]);
+    if (p.do_cfl) {
+      double m = sRed[0];
+      for (int k = 1; k < NT / 64; ++k) m = fmax(m, sRed[k]);
+      atomicMax(&p.ctrl->maxrate, (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ CFL rate of a state
+template <class SYS, int DIM>
+__global__ __launch_bounds__(256) void cfl_kernel(CflParams p) {
+  constexpr int NV = SYS::NV;
+  __shared__ double sRed[4];
+  long long n = (long long)p.nx * p.ny;
+  double rate = 0.0;
+  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
+    int i = (int)(c % p.nx), j = (int)(c / p.nx);
+    long long off = (long long)j * p.pitch + i;
+    double U[NV], W[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v] = p.U[v * p.plane + off];
+    SYS::cons_to_prim(U, W);
+    double r;
+    if constexpr (DIM == 1) r = SYS::template cell_lambda<0>(W, p.sigma_lim, p.kws);
+    else
+      r = SYS::template cell_lambda<0>(W, p.sigma_lim, p.kws) / p.dx +
+          SYS::template cell_lambda<1>(W, p.sigma_lim, p.kws) / p.dy;
+    rate = fmax(rate, r);
+  }
+  rate = wave_max(rate);
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = rate;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+    atomicMax(&p.ctrl->maxrate, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// ------------------------------------------------------------------ time control
+__global__ void finalize_kernel(DevCtrl* c, int dim, double cfl, double dx) {
+  if (threadIdx.x != 0) return;
+  double dt = 0.0;
+  if (c->status == 0) {
+    if (c->dt_fixed > 0.0) {
+      dt = c->dt_fixed;
+    } else {
+      double m = __longlong_as_double((long long)c->maxrate);
+      dt = (dim == 1) ? cfl * dx / m : cfl / m;
+      if (!(m > 0.0)) dt = 0.0;
+    }
+    if (c->t_end > 0.0) {
+      if (c->t >= c->t_end * (1.0 - 1e-14)) dt = 0.0;
+      else dt = fmin(dt, c->t_end - c->t);
+    }
+  }
+  c->dt = dt;
+  c->maxrate = 0ull;
+  if (dt > 0.0) {
+    c->t += dt;
+    c->step += 1;
+    c->dt_last = dt;
+  }
+}
+
+__global__ void ctrl_set_kernel(DevCtrl* c, double dt_fixed, double t_end) {
+  if (threadIdx.x == 0) {
+    c->dt_fixed = dt_fixed;
+    c->t_end = t_end;
+  }
+}
+
+__global__ void ctrl_reset_kernel(DevCtrl* c, double t0) {
+  if (threadIdx.x == 0) {
+    c->dt = 0.0; c->t = t0; c->t_end = 0.0; c->dt_fixed = 0.0; c->dt_last = 0.0;
+    c->maxrate = 0ull; c->step = 0; c->n_fallback = 0; c->status = 0; c->fail_step = 0x7fffffff;
+  }
+}
+
+// ------------------------------------------------------------------ state in / out
+template <class SYS>
+__global__ void ingest_kernel(int repr, const double* src, double* U, int nx, int ny, int pitch,
+                              DevCtrl* c) {
+  constexpr int NV = SYS::NV;
+  long long n = (long long)nx * ny;
+  long long plane = (long long)ny * pitch;
+  int bad = 0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(k % nx), j = (int)(k / nx);
+    double A[NV], Uc[NV], W[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[v] = src[v * n + k];
+    if (repr == 0) {
+      SYS::prim_to_cons(A, Uc);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) W[v] = A[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Uc[v] = A[v];
+      SYS::cons_to_prim(Uc, W);
+    }
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      fin = fin && isfinite(Uc[v]);
+      U[v * plane + (long long)j * pitch + i] = Uc[v];
+    }
+    if (!fin) bad |= ST_NONFINITE;
+    else if (!SYS::admissible(W)) bad |= ST_UNREALIZABLE;
+  }
+  bad = wave_or(bad);
+  if ((threadIdx.x & 63) == 0 && bad) atomicOr(&c->status, bad);
+}
+
+template <class SYS>
+__global__ void egress_kernel(int repr, const double* U, double* dst, int nx, int ny, int pitch) {
+  constexpr int NV = SYS::NV;
+  long long n = (long long)nx * ny;
+  long long plane = (long long)ny * pitch;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(k % nx), j = (int)(k / nx);
+    double Uc[NV], W[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uc[v] = U[v * plane + (long long)j * pitch + i];
+    if (repr == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dst[v * n + k] = Uc[v];
+    } else {
+      SYS::cons_to_prim(Uc, W);
+      if (repr == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dst[v * n + k] = W[v];
+      } else {
+        dst[k] = SYS::sigma(W);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <class SYS, int DIM, int ORDER>
+static hipError_t launch_stage_t(const StageParams& p, hipStream_t s) {
+  if constexpr (DIM == 2) {
+    constexpr int TX = 16, TY = 15, NT = 256;
+    int nb = p.nblk;
+    int grid = ((nb + 7) / 8) * 8;
+    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, TX, TY, NT>), dim3(grid), dim3(NT), 0, s, p);
+  } else {
+    constexpr int TX = 63, TY = 1, NT = 64;
+    int nb = p.nblk;
+    int grid = ((nb + 7) / 8) * 8;
+    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, TX, TY, NT>), dim3(grid), dim3(NT), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(int system, int dim, int order, const StageParams& p, hipStream_t s) {
+  if (system == 5) {
+    if (dim != 1) return hipErrorInvalidValue;
+    return order == 2 ? launch_stage_t<Sys5, 1, 2>(p, s) : launch_stage_t<Sys5, 1, 1>(p, s);
+  }
+  if (dim == 1) return order == 2 ? launch_stage_t<Sys14, 1, 2>(p, s) : launch_stage_t<Sys14, 1, 1>(p, s);
+  return order == 2 ? launch_stage_t<Sys14, 2, 2>(p, s) : launch_stage_t<Sys14, 2, 1>(p, s);
+}
+
+hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s) {
+  long long n = (long long)p.nx * p.ny;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (system == 5) hipLaunchKernelGGL((cfl_kernel<Sys5, 1>), dim3(grid), dim3(256), 0, s, p);
+  else if (dim == 1) hipLaunchKernelGGL((cfl_kernel<Sys14, 1>), dim3(grid), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL((cfl_kernel<Sys14, 2>), dim3(grid), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(DevCtrl* c, int dim, double cfl, double dx, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, c, dim, cfl, dx);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_set(DevCtrl* c, double dt_fixed, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(ctrl_set_kernel, dim3(1), dim3(64), 0, s, c, dt_fixed, t_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_reset(DevCtrl* c, double t0, hipStream_t s) {
+  hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(64), 0, s, c, t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest(int system, int repr, const double* src, double* U, int nx, int ny,
+                         int pitch, DevCtrl* c, hipStream_t s) {
+  long long n = (long long)nx * ny;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 8192) grid = 8192;
+  if (system == 5) hipLaunchKernelGGL((ingest_kernel<Sys5>), dim3(grid), dim3(256), 0, s, repr, src, U, nx, ny, pitch, c);
+  else hipLaunchKernelGGL((ingest_kernel<Sys14>), dim3(grid), dim3(256), 0, s, repr, src, U, nx, ny, pitch, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_egress(int system, int repr, const double* U, double* dst, int nx, int ny,
+                         int pitch, hipStream_t s) {
+  long long n = (long long)nx * ny;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 8192) grid = 8192;
+  if (system == 5) hipLaunchKernelGGL((egress_kernel<Sys5>), dim3(grid), dim3(256), 0, s, repr, U, dst, nx, ny, pitch);
+  else hipLaunchKernelGGL((egress_kernel<Sys14>), dim3(grid), dim3(256), 0, s, repr, U, dst, nx, ny, pitch);
+  return hipGetLastError();
+}
+
+}  // namespace mx

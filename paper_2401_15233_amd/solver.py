@@ -1,0 +1,226 @@
+"""Python binding of ``libmaxent.so`` (the C-ABI in include/maxent.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch provides device buffers and the current HIP stream.  There is no CPU fallback:
+if the library is not built or cannot be loaded, every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libmaxent.so')
+
+MAXENT_OK = 0
+STATUS = {-1: 'INVAL', -2: 'NOMEM', -3: 'DEVICE', -4: 'NONFINITE', -5: 'UNREALIZABLE',
+          -6: 'STATE'}
+BC = {'transmissive': 0, 'periodic': 1, 'reflective': 2, 'jet': 3}
+LIMITER = {'minmod': 0, 'vanalbada': 1}
+FLUX = {'hll': 0, 'rusanov': 1}
+INTEGRATOR = {'fe': 0, 'ssprk2': 1, 'midpoint': 2}
+TAU_MODE = {'local': 0, 'const': 1}
+REPR = {'primitive': 0, 'conserved': 1, 'sigma': 2}
+PRECISION = {'fp64': 0}
+
+EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_moments',
+            'maxent_num_vars', 'maxent_get_info', 'maxent_destroy', 'maxent_last_error',
+            'maxent_abi_version', 'maxent_set_profiling', 'maxent_get_profile')
+
+
+class MaxentError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f'{STATUS.get(code, code)}: {msg}')
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [('system', ctypes.c_int), ('dim', ctypes.c_int), ('nx', ctypes.c_int),
+                ('ny', ctypes.c_int), ('x0', ctypes.c_double), ('x1', ctypes.c_double),
+                ('y0', ctypes.c_double), ('y1', ctypes.c_double), ('bc', ctypes.c_int * 4),
+                ('n_jets', ctypes.c_int), ('jet_yc', ctypes.c_double * 4),
+                ('jet_width', ctypes.c_double * 4), ('jet_angle_deg', ctypes.c_double * 4),
+                ('jet_mach', ctypes.c_double), ('jet_rho', ctypes.c_double),
+                ('jet_T', ctypes.c_double), ('tau_mode', ctypes.c_int),
+                ('rho_ref', ctypes.c_double), ('T_ref', ctypes.c_double)]
+
+
+class Numerics(ctypes.Structure):
+    _fields_ = [('precision', ctypes.c_int), ('order', ctypes.c_int), ('limiter', ctypes.c_int),
+                ('flux', ctypes.c_int), ('integrator', ctypes.c_int), ('cfl', ctypes.c_double),
+                ('sigma_lim', ctypes.c_double), ('k_ws', ctypes.c_double),
+                ('positivity_fallback', ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [('t', ctypes.c_double), ('dt_last', ctypes.c_double),
+                ('steps', ctypes.c_longlong), ('n_fallback', ctypes.c_longlong),
+                ('fail_step', ctypes.c_int), ('fail_code', ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load the HIP library (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f'{path} is not built; run `python -m paper_2401_15233_amd.build`')
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.maxent_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Numerics), vp,
+                                ctypes.POINTER(vp)]
+    L.maxent_init_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double]
+    L.maxent_step.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, ctypes.POINTER(Info)]
+    L.maxent_get_moments.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+    L.maxent_num_vars.argtypes = [vp]
+    L.maxent_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.maxent_destroy.argtypes = [vp]
+    L.maxent_destroy.restype = None
+    L.maxent_last_error.argtypes = [vp]
+    L.maxent_last_error.restype = ctypes.c_char_p
+    L.maxent_abi_version.argtypes = []
+    L.maxent_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.maxent_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_longlong)]
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError('no HIP device visible to torch')
+    return torch
+
+
+def make_problem(system=14, dim=1, nx=100, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                 bc=('transmissive',) * 4, jets=(), jet_mach=3.0, jet_rho=1.0, jet_T=1.0,
+                 tau_mode='local', rho_ref=1.0, T_ref=1.0):
+    p = Problem()
+    p.system, p.dim, p.nx, p.ny = system, dim, nx, ny
+    p.x0, p.x1, p.y0, p.y1 = x0, x1, y0, y1
+    for k, b in enumerate(bc):
+        p.bc[k] = BC[b] if isinstance(b, str) else int(b)
+    p.n_jets = len(jets)
+    for k, (yc, w, ang) in enumerate(jets):
+        p.jet_yc[k], p.jet_width[k], p.jet_angle_deg[k] = yc, w, ang
+    p.jet_mach, p.jet_rho, p.jet_T = jet_mach, jet_rho, jet_T
+    p.tau_mode = TAU_MODE[tau_mode] if isinstance(tau_mode, str) else int(tau_mode)
+    p.rho_ref, p.T_ref = rho_ref, T_ref
+    return p
+
+
+def make_numerics(precision='fp64', order=2, limiter='minmod', flux='hll', integrator='ssprk2',
+                  cfl=0.5, sigma_lim=1e-4, k_ws=1.0, positivity_fallback=True):
+    n = Numerics()
+    n.precision = PRECISION[precision]
+    n.order = order
+    n.limiter = LIMITER[limiter]
+    n.flux = FLUX[flux]
+    n.integrator = INTEGRATOR[integrator]
+    n.cfl, n.sigma_lim, n.k_ws = cfl, sigma_lim, k_ws
+    n.positivity_fallback = int(bool(positivity_fallback))
+    return n
+
+
+_PROBLEM_KEYS = ('system', 'dim', 'nx', 'ny', 'x0', 'x1', 'y0', 'y1', 'bc', 'jets', 'jet_mach',
+                 'jet_rho', 'jet_T', 'tau_mode', 'rho_ref', 'T_ref')
+
+
+class MaxEntSolver:
+    """One solver instance on the current HIP device and stream.
+
+    init_state(W) -> step(n, dt, tau_ref, t_end) -> get('primitive' | 'conserved' | 'sigma').
+    Fields are [nv][ny][nx] float64 (torch CUDA tensors or NumPy arrays on input; torch CUDA
+    tensors on output)."""
+
+    def __init__(self, stream=None, **kw):
+        self._lib = load_library()
+        torch = _torch()
+        pk = {k: v for k, v in kw.items() if k in _PROBLEM_KEYS}
+        nk = {k: v for k, v in kw.items() if k not in _PROBLEM_KEYS}
+        self.problem = make_problem(**pk)
+        self.numerics = make_numerics(**nk)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        rc = self._lib.maxent_create(ctypes.byref(self.problem), ctypes.byref(self.numerics),
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != MAXENT_OK:
+            raise MaxentError(rc, self._lib.maxent_last_error(None).decode())
+        self._h = h
+        self.nv = self._lib.maxent_num_vars(h)
+        self.shape = (self.nv, self.problem.ny, self.problem.nx)
+
+    def _check(self, rc):
+        if rc != MAXENT_OK:
+            raise MaxentError(rc, self._lib.maxent_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, '_h', None):
+            self._lib.maxent_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_state(self, field, repr='primitive', t0=0.0):
+        torch = _torch()
+        if isinstance(field, np.ndarray):
+            a = np.ascontiguousarray(field, dtype=np.float64)
+            if a.size != int(np.prod(self.shape)):
+                raise ValueError(f'field has {a.size} values, expected shape {self.shape}')
+            rc = self._lib.maxent_init_state(self._h, REPR[repr], a.ctypes.data_as(ctypes.c_void_p),
+                                             0, float(t0))
+        else:
+            a = field.to(dtype=torch.float64).contiguous()
+            if a.numel() != int(np.prod(self.shape)) or not a.is_cuda:
+                raise ValueError(f'field must be a CUDA tensor with shape {self.shape}')
+            rc = self._lib.maxent_init_state(self._h, REPR[repr], ctypes.c_void_p(a.data_ptr()), 1,
+                                             float(t0))
+        self._check(rc)
+
+    def step(self, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True):
+        info = Info()
+        rc = self._lib.maxent_step(self._h, int(n), float(dt), float(tau_ref), float(t_end),
+                                   ctypes.byref(info))
+        if check:
+            self._check(rc)
+        d = info.as_dict()
+        d['status'] = STATUS.get(rc, 'OK') if rc else 'OK'
+        return d
+
+    def set_profiling(self, enable=True):
+        self._check(self._lib.maxent_set_profiling(self._h, int(bool(enable))))
+
+    def profile(self):
+        """(total milliseconds, launches) of the stage kernels since profiling was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        self._check(self._lib.maxent_get_profile(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def info(self):
+        info = Info()
+        self._check(self._lib.maxent_get_info(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    def get(self, repr='primitive', out=None):
+        torch = _torch()
+        shape = self.shape if repr != 'sigma' else self.shape[1:]
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device='cuda')
+        self._check(self._lib.maxent_get_moments(self._h, REPR[repr], ctypes.c_void_p(out.data_ptr()), 1))
+        return out

@@ -1,0 +1,165 @@
+"""Test helpers: map solver keyword settings to the oracle's Setup, run both sides on the
+same seeded inputs, compare per moment.  Test infrastructure only."""
+import dataclasses
+
+import numpy as np
+
+from oracle import scheme as sc, moments as mo
+
+SOLVER_TO_SETUP = ('system', 'dim', 'nx', 'ny', 'x0', 'x1', 'y0', 'y1', 'jet_mach', 'jet_rho',
+                   'jet_T', 'tau_mode', 'rho_ref', 'T_ref', 'order', 'limiter', 'flux',
+                   'integrator', 'cfl', 'sigma_lim', 'k_ws', 'positivity_fallback')
+
+
+def to_setup(kw):
+    s = sc.Setup()
+    for k in SOLVER_TO_SETUP:
+        if k in kw:
+            setattr(s, k, kw[k])
+    if 'bc' in kw:
+        s.bc = tuple(kw['bc'])
+    if 'jets' in kw:
+        s.jets = [tuple(j) for j in kw['jets']]
+    return s
+
+
+def prim_to_cons(W, system):
+    return mo.prim_to_cons5(W) if system == 5 else mo.prim_to_cons14(W)
+
+
+def field_rel_err(a, b):
+    """Per-moment error max_i |a - b| / max_i |b| (field-relative, so moments that vanish
+    in part of the field, such as q or P_xy, are compared on the field's own scale)."""
+    a = np.asarray(a, dtype=float).reshape(b.shape[0], -1)
+    b = np.asarray(b, dtype=float).reshape(b.shape[0], -1)
+    out = np.zeros(b.shape[0])
+    for v in range(b.shape[0]):
+        d = np.abs(a[v] - b[v]).max()
+        out[v] = 0.0 if d == 0.0 else d / max(np.abs(b[v]).max(), 1e-300)
+    return out
+
+
+def oracle_run(kw, W0, nsteps=None, dt=0.0, tau_ref=0.0, t_end=0.0):
+    s = to_setup(kw)
+    U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
+    if s.dim == 1:
+        U0 = U0.reshape(U0.shape[0], -1)
+    U, t, n = sc.run(U0, s, tau_ref, nsteps=nsteps, dt=dt if dt > 0 else None,
+                     t_end=t_end if t_end > 0 else None)
+    return U, t, n
+
+
+def oracle_cell_step(W, i, j, kw, dt, tau_ref, r=4):
+    """One full oracle step for the single cell (i, j) of a large 2D field, computed on the
+    (2r+1)^2 patch around it: with two stages of a 2-cell stencil nothing beyond r = 4
+    cells away reaches the centre, so the patch's own ghost cells never matter unless the
+    patch side is a real domain side (where the real boundary condition is kept)."""
+    s = to_setup(kw)
+    ny, nx = W.shape[1:]
+    dx, dy = s.dx, s.dy
+    i0, i1 = max(0, i - r), min(nx, i + r + 1)
+    j0, j1 = max(0, j - r), min(ny, j + r + 1)
+    bc = list(s.bc)
+    if i0 > 0:
+        bc[0] = 'transmissive'
+    if i1 < nx:
+        bc[1] = 'transmissive'
+    if j0 > 0:
+        bc[2] = 'transmissive'
+    if j1 < ny:
+        bc[3] = 'transmissive'
+    sp = dataclasses.replace(s, nx=i1 - i0, ny=j1 - j0, x0=s.x0 + i0 * dx, x1=s.x0 + i1 * dx,
+                             y0=s.y0 + j0 * dy, y1=s.y0 + j1 * dy, bc=tuple(bc))
+    U = mo.prim_to_cons14(W[:, j0:j1, i0:i1])
+    U1 = sc.step(U, dt, sp, tau_ref)
+    return U1[:, j - j0, i - i0]
+
+
+PERTURB = 4 * 2.220446049250313e-16   # 4 ulp relative
+
+
+def oracle_with_spread(kw, W0, nsteps=None, dt=0.0, tau_ref=0.0, t_end=0.0, trials=3, seed=0,
+                       check=True):
+    """The oracle's result and its own spread: the largest change of each output value when
+    the input state is perturbed by +-4 ulp (random signs per value), over `trials` runs.
+    The spread measures the conditioning of the step on this input; any FP64
+    implementation that rounds differently (FMA contraction, other libm, other operation
+    order) can differ from the oracle by about this much."""
+    s = to_setup(kw)
+    U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
+    if s.dim == 1:
+        U0 = U0.reshape(U0.shape[0], -1)
+    kwr = dict(nsteps=nsteps, dt=dt if dt > 0 else None, t_end=t_end if t_end > 0 else None,
+               check=check)
+    base, t, n = sc.run(U0, s, tau_ref, **kwr)
+    rng = np.random.default_rng(seed)
+    spread = np.zeros_like(base)
+    for _ in range(trials):
+        Up = U0 * (1.0 + rng.choice([-1.0, 1.0], U0.shape) * PERTURB)
+        out, _, _ = sc.run(Up, s, tau_ref, **kwr)
+        spread = np.maximum(spread, np.abs(out - base))
+    return base, spread, t, n
+
+
+def within_spread(gpu, base, spread, rel_floor=1e-12, factor=2.0):
+    """Per cell and moment: |gpu - oracle| <= rel_floor * max|oracle_v| + factor * spread.
+    Returns (ok, worst excess ratio, per-moment field-relative error)."""
+    g = np.asarray(gpu, dtype=float).reshape(base.shape[0], -1)
+    b = base.reshape(base.shape[0], -1)
+    sp = spread.reshape(base.shape[0], -1)
+    scale = np.maximum(np.abs(b).max(1, keepdims=True), 1e-300)
+    d = np.abs(g - b)
+    bound = rel_floor * scale + factor * sp
+    ratio = np.where(d == 0.0, 0.0, d / np.maximum(bound, 1e-300))
+    err = np.where(d.max(1) == 0.0, 0.0, d.max(1) / scale[:, 0])
+    return bool(ratio.max() <= 1.0), float(ratio.max()), err
+
+
+def oracle_cells_1d(W, cells, kw, nsteps, dt, tau_ref, trials=2, seed=0):
+    """Oracle values after `nsteps` fixed-dt steps at selected cells of a long 1D field, each
+    computed on the patch [i - 4 nsteps, i + 4 nsteps] (the dependency cone of SSP-RK2 with
+    a two-cell stencil per stage); a patch side inside the domain gets transmissive ghosts,
+    which never reach the centre.  Also returns the +-4 ulp perturbation spread."""
+    s = to_setup(kw)
+    nx = W.shape[-1]
+    r = 4 * nsteps
+    rng = np.random.default_rng(seed)
+    vals, spreads = [], []
+    for i in cells:
+        i0, i1 = max(0, i - r), min(nx, i + r + 1)
+        bc = list(s.bc)
+        if i0 > 0:
+            bc[0] = 'transmissive'
+        if i1 < nx:
+            bc[1] = 'transmissive'
+        if bc[0] == 'periodic' or bc[1] == 'periodic':
+            raise ValueError('periodic fields are not patchable')
+        sp = dataclasses.replace(s, nx=i1 - i0, x0=s.x0 + i0 * s.dx, x1=s.x0 + i1 * s.dx,
+                                 bc=tuple(bc))
+        U = prim_to_cons(W[:, i0:i1], s.system)
+        base, _, _ = sc.run(U, sp, tau_ref, nsteps=nsteps, dt=dt, check=False)
+        spread = np.zeros(base.shape[0])
+        for _ in range(trials):
+            Up = U * (1.0 + rng.choice([-1.0, 1.0], U.shape) * PERTURB)
+            out, _, _ = sc.run(Up, sp, tau_ref, nsteps=nsteps, dt=dt, check=False)
+            spread = np.maximum(spread, np.abs(out[:, i - i0] - base[:, i - i0]))
+        vals.append(base[:, i - i0])
+        spreads.append(spread)
+    return np.array(vals).T, np.array(spreads).T
+
+
+def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=2, seed=0):
+    """Long runs: the oracle's result at t_end and its L1 spread per moment (largest
+    ||perturbed - base||_1 over +-4 ulp input perturbations)."""
+    s = to_setup(kw)
+    U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
+    if s.dim == 1:
+        U0 = U0.reshape(U0.shape[0], -1)
+    base, t, n = sc.run(U0, s, tau_ref, t_end=t_end)
+    rng = np.random.default_rng(seed)
+    spread = np.zeros(base.shape[0])
+    for _ in range(trials):
+        Up = U0 * (1.0 + rng.choice([-1.0, 1.0], U0.shape) * PERTURB)
+        out, _, _ = sc.run(Up, s, tau_ref, t_end=t_end)
+        spread = np.maximum(spread, np.abs(out - base).reshape(base.shape[0], -1).sum(1))
+    return base, spread, t, n

@@ -1,0 +1,80 @@
+"""The C-ABI library loads, exports every symbol include/maxent.h declares, and validates
+arguments before touching a device (no compute calls here: no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2401_15233_amd import solver as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'maxent.h')
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    return sorted(set(re.findall(r'\b(maxent_[a-z_]+)\s*\(', text)))
+
+
+@pytest.fixture(scope='module')
+def lib():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.fail('libmaxent.so is not built (run python -m paper_2401_15233_amd.build)')
+    return S.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(S.EXPORTED) <= set(names)
+
+
+def test_abi_version(lib):
+    assert lib.maxent_abi_version() == 1
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the header structs have the C layout (size and field offsets)."""
+    assert ctypes.sizeof(S.Problem) == 4 * 4 + 4 * 8 + 4 * 4 + 4 + 4 + 12 * 8 + 3 * 8 + 8 + 2 * 8
+    assert S.Problem.x0.offset == 16 and S.Problem.n_jets.offset == 64
+    assert ctypes.sizeof(S.Numerics) == 5 * 4 + 4 + 3 * 8 + 8
+    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4
+
+
+@pytest.mark.parametrize('bad', [
+    dict(system=7), dict(system=5, dim=2, ny=8), dict(nx=2), dict(dim=1, ny=4),
+    dict(bc=('periodic', 'transmissive', 'transmissive', 'transmissive')),
+    dict(dim=2, ny=8, bc=('transmissive', 'jet', 'transmissive', 'transmissive')),
+    dict(bc=('jet', 'transmissive', 'transmissive', 'transmissive')),
+    dict(x1=-1.0)])
+def test_create_rejects_bad_problem(lib, bad):
+    kw = dict(system=14, dim=1, nx=16, ny=1)
+    kw.update(bad)
+    p = S.make_problem(**kw)
+    n = S.make_numerics()
+    h = ctypes.c_void_p()
+    rc = lib.maxent_create(ctypes.byref(p), ctypes.byref(n), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert len(lib.maxent_last_error(None)) > 0
+
+
+@pytest.mark.parametrize('bad', [dict(order=3), dict(cfl=0.0), dict(cfl=1.5), dict(sigma_lim=0.0),
+                                 dict(k_ws=0.5)])
+def test_create_rejects_bad_numerics(lib, bad):
+    p = S.make_problem(system=14, dim=1, nx=16)
+    n = S.make_numerics(**bad)
+    h = ctypes.c_void_p()
+    assert lib.maxent_create(ctypes.byref(p), ctypes.byref(n), None, ctypes.byref(h)) == -1
+
+
+def test_null_handle_calls_are_rejected(lib):
+    info = S.Info()
+    assert lib.maxent_step(None, 1, 0.0, 0.0, 0.0, ctypes.byref(info)) == -1
+    assert lib.maxent_init_state(None, 0, None, 0, 0.0) == -1
+    assert lib.maxent_get_moments(None, 0, None, 0) == -1
+    assert lib.maxent_num_vars(None) == 0
+    lib.maxent_destroy(None)

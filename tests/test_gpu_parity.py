@@ -1,0 +1,327 @@
+"""GPU (HIP, through the C-ABI) vs the CPU oracle on identical seeded inputs.
+
+Bar, per cell and moment: |gpu - oracle| <= 1e-12 * max|oracle_v| + 2 * spread, where the
+spread is the oracle's own change under +-4 ulp perturbations of its input (computed by the
+oracle alone).  Where the step is well conditioned (1D Sod, smooth fields) the spread is far
+below 1e-12 and the bar is the workload's FP64 tolerance of 1e-12 relative; where it is not
+(supersonic beams: |u|^2/T ~ 15 makes primitive recovery cancel, and the closure and wave
+speeds amplify the cancelled heat flux) no FP64 implementation, the oracle included, can
+agree to 1e-12, and the measured spread states how far apart two correct ones may be.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2401_15233_amd import inputs as I
+from oracle import scheme as sc, moments as mo
+import oracle_bridge as ob
+
+pytestmark = pytest.mark.gpu
+
+TOL1 = 1e-12
+
+SOD5 = dict(system=5, dim=1, nx=1000, order=1, integrator='fe', flux='hll', cfl=0.5,
+            bc=('transmissive',) * 4)
+SOD14 = dict(system=14, dim=1, nx=200, order=2, integrator='ssprk2', flux='hll', cfl=0.5,
+             limiter='minmod', bc=('transmissive',) * 4)
+JETS = dict(system=14, dim=2, order=2, integrator='ssprk2', flux='hll', cfl=0.4,
+            limiter='minmod', bc=('jet', 'transmissive', 'transmissive', 'transmissive'),
+            jets=[(0.35, 0.1, 30.0), (0.65, 0.1, -30.0)], jet_mach=3.0, jet_rho=1.0, jet_T=1.0)
+TAU_SOD = I.kn_to_tau_ref(0.01)
+TAU_JET = I.kn_to_tau_ref(0.1, L_ref=0.1)
+
+
+def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True):
+    s = S.MaxEntSolver(**kw)
+    s.init_state(np.ascontiguousarray(W0))
+    info = s.step(n, dt=dt, tau_ref=tau_ref, t_end=t_end, check=check)
+    U = s.get('conserved').cpu().numpy()
+    s.close()
+    return U, info
+
+
+def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, trials=3):
+    """Run both sides, print the errors, assert the condition-aware bar."""
+    Ug, info = gpu_run(S, kw, W0, n if n is not None else 20000, dt, tau_ref, t_end, check)
+    base, spread, t, nst = ob.oracle_with_spread(kw, W0, nsteps=n, dt=dt, tau_ref=tau_ref,
+                                                  t_end=t_end, trials=trials, check=check)
+    ok, ratio, err = ob.within_spread(Ug, base, spread)
+    sp = (spread.reshape(spread.shape[0], -1).max(1) /
+          np.maximum(np.abs(base.reshape(base.shape[0], -1)).max(1), 1e-300))
+    print(f'{name}: field-relative error max {err.max():.2e}, oracle spread max {sp.max():.2e}, '
+          f'bound use {ratio:.2f}; steps gpu {info["steps"]} oracle {nst}', flush=True)
+    print(f'   per moment {np.array2string(err, precision=1)}', flush=True)
+    assert ok, f'{name}: error exceeds 1e-12 + 2 x oracle spread (ratio {ratio:.2f})'
+    return Ug, info, base, t, nst
+
+
+def report(name, err):
+    print(f'{name}: max field-relative error {err.max():.3e} (per moment {np.array2string(err, precision=1)})',
+          flush=True)
+
+
+# ------------------------------------------------------------------ 1D
+def test_sod5_first_order_one_step(gpu_lib):
+    Ug, info, base, t, n = compare('sod5 1 step', gpu_lib, SOD5, I.sod_prims(5, 1000), 1,
+                                   tau_ref=TAU_SOD)
+    assert abs(info['t'] - t) <= 1e-15 * t
+
+
+def test_sod5_full_run_to_t_end(gpu_lib):
+    """The 5-moment Sod workload in full: 1000 cells, first order, HLL, FE, Kn = 0.01,
+    t = 0.2 (about 14000 CFL steps).  The CFL step jumps between near-Junk cells, so the
+    trajectory is sensitive: the oracle itself moves by about 1e-2 pointwise under +-4 ulp
+    input perturbations.  Long runs are therefore compared in L1 at t = 0.2:
+    ||gpu - oracle||_1 <= 1e-12 ||oracle||_1 + 2 x the oracle's own L1 spread."""
+    W0 = I.sod_prims(5, 1000)
+    Ug, info = gpu_run(gpu_lib, SOD5, W0, 20000, tau_ref=TAU_SOD, t_end=0.2)
+    base, spread, t, n = ob.oracle_with_l1_spread(SOD5, W0, 0.2, TAU_SOD)
+    d1 = np.abs(Ug.reshape(5, -1) - base).sum(1)
+    b1 = np.abs(base).sum(1)
+    print(f'sod5 full: L1 relative error {np.array2string(d1 / b1, precision=2)}, '
+          f'oracle L1 spread {np.array2string(spread / b1, precision=2)}; '
+          f'steps gpu {info["steps"]} oracle {n}', flush=True)
+    assert abs(info['t'] - 0.2) < 1e-14 and abs(info['steps'] - n) <= max(2, n // 1000)
+    assert np.all(d1 <= 1e-12 * b1 + 2 * spread)
+
+
+@pytest.mark.parametrize('nx', [200, 63, 64, 5])
+def test_sod14_muscl_rk2_one_step(gpu_lib, nx):
+    compare(f'sod14 nx={nx} 1 step', gpu_lib, dict(SOD14, nx=nx), I.sod_prims(14, nx), 1,
+            tau_ref=TAU_SOD)
+
+
+def test_sod14_muscl_rk2_many_steps(gpu_lib):
+    Ug, info, base, t, n = compare('sod14 60 steps', gpu_lib, SOD14, I.sod_prims(14, 200), 60,
+                                   tau_ref=TAU_SOD)
+    assert abs(info['t'] - t) < 1e-12 * t
+
+
+@pytest.mark.parametrize('kn', [1e-3, 1e-2, 0.1, 1.0, 10.0])
+def test_sod14_knudsen_sweep_20000_cells(gpu_lib, kn):
+    """The 14-moment Sod workload at full size (20000 cells) for each Knudsen number of the
+    sweep: 6 steps at the oracle's initial CFL step; sampled cells (edges, tile seams, the
+    diaphragm region, random) recomputed by the oracle on patches spanning their cone."""
+    nx = 20000
+    kw = dict(SOD14, nx=nx)
+    W0 = I.sod_prims(14, nx)
+    tau = I.kn_to_tau_ref(kn)
+    setup = ob.to_setup(kw)
+    dt = sc.cfl_dt(mo.prim_to_cons14(W0), setup)
+    Ug, info = gpu_run(gpu_lib, kw, W0, 6, dt=dt, tau_ref=tau)
+    Ug = Ug[:, 0, :]
+    rng = np.random.default_rng(int(kn * 1000) + 7)
+    cells = [0, 1, 62, 63, 126, 9990, 9995, 9999, 10000, 10004, 10011, 19998, 19999]
+    cells += [int(c) for c in rng.integers(9970, 10030, 10)] + [int(c) for c in rng.integers(0, nx, 5)]
+    vals, spread = ob.oracle_cells_1d(W0, cells, kw, 6, dt, tau)
+    scale = np.maximum(np.maximum(np.abs(mo.prim_to_cons14(W0)).max(1), np.abs(vals).max(1)),
+                       1e-300)[:, None]
+    d = np.abs(Ug[:, cells] - vals)
+    ratio = np.max(np.where(d == 0, 0.0, d / (TOL1 * scale + 2 * spread)))
+    report(f'sod14 20000 cells Kn={kn}', (d / scale).max(1))
+    print(f'   bound use {ratio:.2f}', flush=True)
+    assert ratio <= 1.0
+
+
+@pytest.mark.parametrize('variant', [
+    dict(flux='rusanov'), dict(limiter='vanalbada'), dict(integrator='midpoint'),
+    dict(integrator='fe'), dict(order=1), dict(k_ws=1.2), dict(tau_mode='const'),
+    dict(bc=('reflective', 'reflective', 'transmissive', 'transmissive')),
+    dict(bc=('periodic', 'periodic', 'transmissive', 'transmissive'))])
+def test_sod14_variants(gpu_lib, variant):
+    kw = dict(SOD14, nx=130)
+    kw.update(variant)
+    W0 = I.random_smooth_field14(130, 1, seed=5)[:, 0, :]
+    for n_steps in (1, 6):
+        compare(f'{variant} {n_steps} steps', gpu_lib, kw, W0, n_steps, tau_ref=0.05)
+
+
+def test_random_states_one_step_collisionless(gpu_lib):
+    """Cells drawn from every state family (beams, particle sets, near-equilibrium clouds),
+    periodic, first order, so every face sees two unrelated states; collisionless.  Such a
+    field may legitimately leave the realizable set after a step; both sides report it."""
+    W0 = I.random_states14(600, seed=31)
+    kw = dict(SOD14, nx=600, order=1, bc=('periodic',) * 4, cfl=0.3)
+    compare('random states', gpu_lib, kw, W0, 1, tau_ref=0.0, check=False)
+
+
+# ------------------------------------------------------------------ 2D
+def test_jets_2d_developed_field(gpu_lib):
+    nx, ny = 70, 50   # ragged: 4 tiles of 16 + 6, 3 tiles of 15 + 5
+    kw = dict(JETS, nx=nx, ny=ny)
+    W0 = I.crossed_jets_developed(nx, ny, seed=2)
+    for n_steps in (1, 4):
+        Ug, info, base, t, n = compare(f'jets 70x50 {n_steps} steps', gpu_lib, kw, W0, n_steps,
+                                       tau_ref=TAU_JET)
+        assert abs(info['t'] - t) < 1e-12 * t
+
+
+def test_jets_2d_from_rest_first_order(gpu_lib):
+    nx, ny = 48, 40
+    kw = dict(JETS, nx=nx, ny=ny, order=1, integrator='fe', cfl=0.5)
+    compare('jets from rest FE', gpu_lib, kw, I.crossed_jets_initial(nx, ny), 5, tau_ref=0.0)
+
+
+def test_jets_2d_from_rest_second_order(gpu_lib):
+    nx, ny = 64, 60
+    kw = dict(JETS, nx=nx, ny=ny)
+    compare('jets from rest MUSCL+RK2', gpu_lib, kw, I.crossed_jets_initial(nx, ny), 12,
+            tau_ref=TAU_JET)
+
+
+def test_2d_periodic_reflective_smooth(gpu_lib):
+    nx, ny = 40, 33
+    kw = dict(JETS, nx=nx, ny=ny, bc=('periodic', 'periodic', 'reflective', 'reflective'),
+              jets=[], integrator='midpoint', limiter='vanalbada', flux='rusanov')
+    compare('2d periodic/reflective', gpu_lib, kw, I.random_smooth_field14(nx, ny, seed=8), 3,
+            tau_ref=0.03)
+
+
+# ------------------------------------------------------------------ full size
+def test_full_size_jets_step_on_sampled_cells(gpu_lib):
+    """2048^2, the launch configuration the benchmark times: one SSP-RK2 step of a
+    developed crossed-jets field with the oracle's CFL step; sampled cells (corners, edges,
+    jet inlet rows, tile seams, interior) recomputed by the oracle one by one on 9x9 patches,
+    with the same perturbation spread as the other tests."""
+    n = 2048
+    kw = dict(JETS, nx=n, ny=n)
+    W0 = I.crossed_jets_developed(n, n, seed=4)
+    dt = oracle_cfl_dt(kw, W0)
+    Ug, info = gpu_run(gpu_lib, kw, W0, 1, dt=dt, tau_ref=TAU_JET)
+    rng = np.random.default_rng(9)
+    cells = [(0, 0), (n - 1, 0), (0, n - 1), (n - 1, n - 1), (0, 614), (0, 818), (1, 1229),
+             (0, 1433), (2, 700), (n - 1, 1024), (1024, 0), (1024, n - 1), (15, 14), (16, 15)]
+    cells += [tuple(int(x) for x in rng.integers(0, n, 2)) for _ in range(20)]
+    cells += [(int(rng.integers(0, 700)), int(rng.integers(600, 1450))) for _ in range(20)]
+    scale = np.maximum(np.abs(mo.prim_to_cons14(W0[:, ::8, ::8])).reshape(14, -1).max(1), 1e-300)
+    worst_ratio, worst_err = 0.0, np.zeros(14)
+    prng = np.random.default_rng(1)
+    for (i, j) in cells:
+        uo = ob.oracle_cell_step(W0, i, j, kw, dt, TAU_JET)
+        spread = np.zeros(14)
+        for _ in range(2):
+            Wp = W0.copy()
+            Wp[:, max(0, j - 4):j + 5, max(0, i - 4):i + 5] *= 1.0 + prng.choice(
+                [-1.0, 1.0], Wp[:, max(0, j - 4):j + 5, max(0, i - 4):i + 5].shape) * ob.PERTURB
+            spread = np.maximum(spread, np.abs(ob.oracle_cell_step(Wp, i, j, kw, dt, TAU_JET) - uo))
+        d = np.abs(Ug[:, j, i] - uo)
+        bound = TOL1 * scale + 2 * spread
+        worst_ratio = max(worst_ratio, float(np.max(np.where(d == 0, 0.0, d / bound))))
+        worst_err = np.maximum(worst_err, d / scale)
+    report('2048^2 sampled cells', worst_err)
+    print(f'   bound use {worst_ratio:.2f}', flush=True)
+    assert worst_ratio <= 1.0
+
+
+def oracle_cfl_dt(kw, W0):
+    setup = ob.to_setup(kw)
+    rate = 0.0
+    for j0 in range(0, W0.shape[1], 256):
+        U = mo.prim_to_cons14(W0[:, j0:j0 + 256])
+        r = sc.cell_lambda(U, setup, 0) / setup.dx + sc.cell_lambda(U, setup, 1) / setup.dy
+        rate = max(rate, r.max())
+    return setup.cfl / rate
+
+
+def test_full_size_cfl_time_step(gpu_lib):
+    """The first CFL step at 2048^2 equals the oracle's CFL step of the same field."""
+    n = 2048
+    kw = dict(JETS, nx=n, ny=n)
+    W0 = I.crossed_jets_developed(n, n, seed=4)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(W0)
+    info = s.step(1, tau_ref=TAU_JET)
+    s.close()
+    dt = oracle_cfl_dt(kw, W0)
+    assert abs(info['dt_last'] - dt) < 1e-13 * dt
+
+
+def test_full_size_periodic_conservation(gpu_lib):
+    """Sum rho, sum rho u_i, sum tr E are conserved with periodic boundaries (BGK conserves
+    them, fluxes telescope) at 2048^2 after a few steps."""
+    n = 2048
+    kw = dict(JETS, nx=n, ny=n, bc=('periodic',) * 4, jets=[])
+    W0 = I.random_smooth_field14(n, n, seed=12)
+    U0 = mo.prim_to_cons14(W0)
+    Ug, info = gpu_run(gpu_lib, kw, W0, 3, tau_ref=0.02)
+    for comp in ([0], [1], [2], [3], [4, 7, 9]):
+        a = U0[comp].sum()
+        b = Ug[comp].sum()
+        assert abs(a - b) < 1e-12 * np.abs(U0[comp]).sum(), comp
+
+
+# ------------------------------------------------------------------ behaviour
+def test_bitwise_deterministic(gpu_lib):
+    kw = dict(JETS, nx=96, ny=90)
+    W0 = I.crossed_jets_developed(96, 90, seed=3)
+    a, _ = gpu_run(gpu_lib, kw, W0, 3, tau_ref=TAU_JET)
+    b, _ = gpu_run(gpu_lib, kw, W0, 3, tau_ref=TAU_JET)
+    assert np.array_equal(a, b)
+
+
+def test_t_end_clipping_and_noop_steps(gpu_lib):
+    W0 = I.sod_prims(14, 100)
+    kw = dict(SOD14, nx=100)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(W0)
+    info = s.step(1000, tau_ref=TAU_SOD, t_end=0.01)
+    assert info['t'] == pytest.approx(0.01, abs=1e-15)
+    U1 = s.get('conserved').cpu().numpy()
+    info2 = s.step(5, tau_ref=TAU_SOD, t_end=0.01)
+    assert info2['steps'] == info['steps']
+    assert np.array_equal(U1, s.get('conserved').cpu().numpy())
+    Uo, t, n = ob.oracle_run(kw, W0, tau_ref=TAU_SOD, t_end=0.01)
+    assert n == info['steps']
+    assert ob.field_rel_err(U1, Uo).max() < 1e-11
+    s.close()
+
+
+def test_fe_pingpong_with_t_end(gpu_lib):
+    kw = dict(SOD5, nx=120)
+    W0 = I.sod_prims(5, 120)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(W0)
+    info = s.step(7, tau_ref=TAU_SOD, t_end=0.004)
+    Ug = s.get('conserved').cpu().numpy()
+    Uo, t, n = ob.oracle_run(kw, W0, tau_ref=TAU_SOD, t_end=0.004)
+    assert n == info['steps'] and n < 7
+    assert ob.field_rel_err(Ug, Uo).max() < 1e-11
+    s.close()
+
+
+def test_primitive_and_sigma_readback(gpu_lib):
+    from oracle import closure as cl
+    W0 = I.random_states14(300, seed=44)
+    kw = dict(SOD14, nx=300)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(W0)
+    Wg = s.get('primitive').cpu().numpy()[:, 0, :]
+    sig = s.get('sigma').cpu().numpy()[0]
+    s.close()
+    assert ob.field_rel_err(Wg, W0).max() < 1e-12
+    sig_o = cl.closure14(W0, 1e-4)[3]
+    assert np.max(np.abs(sig - sig_o)) < 1e-10
+
+
+def test_unrealizable_init_is_rejected(gpu_lib):
+    W0 = I.sod_prims(14, 64)
+    W0[0, 10] = -1.0
+    s = gpu_lib.MaxEntSolver(**dict(SOD14, nx=64))
+    with pytest.raises(gpu_lib.MaxentError) as e:
+        s.init_state(W0)
+    assert e.value.status == 'UNREALIZABLE'
+    with pytest.raises(gpu_lib.MaxentError) as e:
+        s.step(1, tau_ref=TAU_SOD)
+    assert e.value.status == 'STATE'
+    s.close()
+
+
+def test_oversized_fixed_dt_reports_failure_step(gpu_lib):
+    W0 = I.sod_prims(14, 64)
+    s = gpu_lib.MaxEntSolver(**dict(SOD14, nx=64))
+    s.init_state(W0)
+    info = s.step(3, dt=5.0, tau_ref=TAU_SOD, check=False)
+    assert info['status'] in ('NONFINITE', 'UNREALIZABLE')
+    assert info['fail_step'] == 1
+    s.close()
