@@ -24,9 +24,45 @@ sys.path.insert(0, ROOT)
 
 N = 2048
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 # algorithmic HBM bytes per cell and stage launch: stage 1 reads U^n and writes U*
 # (2 x 112 B), stage 2 reads U* and U^n and writes U^{n+1} (3 x 112 B)
 BYTES_PER_CELL_STAGE = {1: 224.0, 2: 336.0}
+# algorithmic FP64 operations per cell and stage launch (each face once per stage, no halo
+# redundancy; add/sub/mul = 1, fma = 2, div/sqrt/exp/log = 1), counted by running the
+# library's own templated device code with a counting scalar:
+# paper_2401_15233_amd/csrc/flopcount.cpp (tests/test_flopcount.py keeps these in sync)
+FLOPS_PER_CELL_STAGE = {1: 4791, 2: 5191}
+SOURCES_FOR_TRAFFIC = ('paper_2401_15233_amd/csrc/mx_kernels.hip',
+                       'paper_2401_15233_amd/csrc/mx_physics.hpp',
+                       'paper_2401_15233_amd/csrc/mx_scheme.hpp',
+                       'paper_2401_15233_amd/csrc/mx_internal.hpp')
+TRAFFIC_PROFILE = 'profiles/stage_kernel_jets2048_fp64_hbm_traffic.txt'
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOURCES_FOR_TRAFFIC:
+        with open(os.path.join(ROOT, f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ':' in line and not line.startswith(' '):
+            k, v = line.split(':', 1)
+            kv[k.strip()] = v.strip()
+    if kv.get('kernel_source_hash') != kernel_source_hash():
+        return None
+    return float(kv['hbm_bytes_per_launch'])
 
 
 def jets_kwargs(n):
@@ -67,6 +103,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=3)
     ap.add_argument('--n', type=int, default=N)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='only run a plain 2 GiB device copy (HBM counter calibration)')
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
         print('bench.py runs on exactly one GPU: the solver has no multi-GPU path (the '
@@ -78,6 +116,15 @@ def main():
     from paper_2401_15233_amd import solver, inputs
 
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        m = 256 * 1024 * 1024
+        src = torch.ones(m, dtype=torch.float64, device='cuda')
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({'copy_kernel_bytes_read': m * 8, 'copy_kernel_bytes_written': m * 8}))
+        return
     n = a.n
     kw = jets_kwargs(n)
     tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
@@ -102,7 +149,9 @@ def main():
     cups = cells * a.steps / (ms / 1e3)
     avg_stage_ms = stage_ms / max(launches, 1)
     bytes_per_launch = cells * 0.5 * (BYTES_PER_CELL_STAGE[1] + BYTES_PER_CELL_STAGE[2])
-    achieved = bytes_per_launch / (avg_stage_ms / 1e3) / 1e9
+    flops_per_launch = cells * 0.5 * (FLOPS_PER_CELL_STAGE[1] + FLOPS_PER_CELL_STAGE[2])
+    achieved = flops_per_launch / (avg_stage_ms / 1e3) / 1e12
+    hbm_achieved = bytes_per_launch / (avg_stage_ms / 1e3) / 1e9
     out = {
         'metric': 'cell-updates/s (14-moment 2D crossed jets, FP64)',
         'value': cups,
@@ -121,10 +170,15 @@ def main():
                    'steps_in_workload': 2000},
         'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms / 1e3) / 1e9,
         'sim_time_reached': info['t'],
-        'roofline': {'bound': 'hbm', 'achieved': achieved, 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
-                     'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
-                     'kernel': 'stage_kernel<Sys14,2,2>', 'avg_launch_ms': avg_stage_ms,
-                     'launches': launches},
+        'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VECTOR_PEAK_TFLOPS,
+                     'unit': 'TFLOP/s', 'frac': achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     'traffic': measured_traffic(),
+                     'kernel': 'stage_kernel<Sys14,2,2,16,15,256> (FP64)',
+                     'avg_launch_ms': avg_stage_ms, 'launches': launches,
+                     'flops_per_launch': flops_per_launch,
+                     'hbm_algorithmic_bytes_per_launch': bytes_per_launch,
+                     'hbm_achieved_gbs': hbm_achieved,
+                     'hbm_frac': hbm_achieved / HBM_PEAK_GBS},
     }
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()

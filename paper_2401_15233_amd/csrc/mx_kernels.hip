@@ -16,6 +16,7 @@
 // per thread.  The 1D tile is 63 cells for one 64-wide wavefront: 64 faces.
 #include "mx_internal.hpp"
 #include "mx_physics.hpp"
+#include "mx_scheme.hpp"
 
 namespace mx {
 
@@ -90,71 +91,6 @@ __device__ __forceinline__ void load_prims(const StageParams& p, const double* U
         }
       }
     }
-  }
-}
-
-// ------------------------------------------------------------------ limiter
-template <class SYS>
-__device__ __forceinline__ double limiter_factor(const double* Wm, const double* Wc,
-                                                 const double* Wp, int kind) {
-  constexpr int NV = SYS::NV;
-  double sc[NV];
-  SYS::scales(Wc, sc);
-  double phi = 1.0;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double a = Wc[v] - Wm[v];
-    double b = Wp[v] - Wc[v];
-    double aa = fabs(a), ab = fabs(b);
-    double f;
-    if (aa + ab <= 1e-10 * sc[v]) f = 1.0;
-    else if (a * b <= 0.0) f = 0.0;
-    else if (kind == 0) f = 2.0 * fmin(aa, ab) / (aa + ab);
-    else f = 2.0 * a * b / (a * a + b * b);
-    phi = fmin(phi, f);
-  }
-  return phi;
-}
-
-template <class SYS>
-__device__ __forceinline__ void face_state(const double* Wm, const double* Wc, const double* Wp,
-                                           double phi, double sgn, double* Wf) {
-#pragma unroll
-  for (int v = 0; v < SYS::NV; ++v) {
-    double a = Wc[v] - Wm[v];
-    double b = Wp[v] - Wc[v];
-    double s = phi * (a + b) / 2.0;
-    Wf[v] = Wc[v] + sgn * (s / 2.0);
-  }
-}
-
-// ------------------------------------------------------------------ face flux
-template <class SYS, int D>
-__device__ __forceinline__ void face_flux(const double* WL, const double* WR, const StageParams& p,
-                                          double* Fh) {
-  constexpr int NV = SYS::NV;
-  double UL[NV], FL[NV], UR[NV], FR[NV];
-  double lminL, lmaxL, lminR, lmaxR;
-  SYS::template face_terms<D>(WL, p.sigma_lim, p.kws, UL, FL, lminL, lmaxL);
-  SYS::template face_terms<D>(WR, p.sigma_lim, p.kws, UR, FR, lminR, lmaxR);
-  if (p.flux == 0) {
-    double SL = fmin(lminL, lminR), SR = fmax(lmaxL, lmaxR);
-    if (SL >= 0.0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fh[v] = FL[v];
-    } else if (SR <= 0.0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fh[v] = FR[v];
-    } else {
-      double inv = 1.0 / (SR - SL);
-      double SLR = SL * SR;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fh[v] = (SR * FL[v] - SL * FR[v] + SLR * (UR[v] - UL[v])) * inv;
-    }
-  } else {
-    double am = fmax(fmax(fabs(lminL), fabs(lmaxL)), fmax(fabs(lminR), fabs(lmaxR)));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * am * (UR[v] - UL[v]);
   }
 }
 
@@ -277,7 +213,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       lds(fi - 1, fj, WL); lds(fi, fj, WR);
     }
     double Fh[NV];
-    face_flux<SYS, 0>(WL, WR, p, Fh);
+    face_flux<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
   }
@@ -298,7 +234,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       } else {
         lds(fi, fj - 1, WL); lds(fi, fj, WR);
       }
-      if constexpr (SYS::NV == 14) face_flux<SYS, 1>(WL, WR, p, Fy);
+      if constexpr (SYS::NV == 14) face_flux<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
     }
   }
   __syncthreads();

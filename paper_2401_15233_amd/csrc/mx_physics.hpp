@@ -120,7 +120,8 @@ struct Sys14 {
 
   template <class T> MX_HD static void cons_to_prim(const T* U, T* W) {
     T rho = U[0];
-    T u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+    T ir = T(1) / rho;
+    T u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
     T P[6];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -165,7 +166,7 @@ struct Sys14 {
     U[13] = rho * uu * uu + T(2) * uu * trP + T(4) * uPu + T(4) * uq + W[13];
   }
 
-  template <class T> MX_HD static T pressure(const T* W) { return (W[4] + W[7] + W[9]) / T(3); }
+  template <class T> MX_HD static T pressure(const T* W) { return (W[4] + W[7] + W[9]) * T(1.0 / 3.0); }
 
   template <class T> MX_HD static bool admissible(const T* W) { return spd_ok(W[0], W + 4); }
 
@@ -173,7 +174,7 @@ struct Sys14 {
   // test of the common limiter
   template <class T> MX_HD static void scales(const T* W, T* sc) {
     T rho = tabs(W[0]);
-    T p = tabs(W[4] + W[7] + W[9]) / T(3);
+    T p = tabs(W[4] + W[7] + W[9]) * T(1.0 / 3.0);
     T c = msqrt(p / rho);
     T c3 = rho * c * c * c;
     sc[0] = rho;
@@ -198,16 +199,17 @@ struct Sys14 {
 
   template <class T> MX_HD static void core(const T* W, T sigma_lim, Core<T>& k) {
     k.rho = W[0];
-    T p = (W[4] + W[7] + W[9]) / T(3);
-    k.c = msqrt(p / k.rho);
+    T p = (W[4] + W[7] + W[9]) * T(1.0 / 3.0);
+    T irho = T(1) / k.rho;
     T ip = T(1) / p;
+    k.c = msqrt(p * irho);
+    T ic = msqrt(k.rho * ip);          // 1 / c
 #pragma unroll
     for (int m = 0; m < 6; ++m) k.Ph[m] = W[4 + m] * ip;
-    T s3 = k.rho * (k.c * k.c * k.c);
-    T is3 = T(1) / s3;
+    T is3 = irho * (ic * ic * ic);     // 1 / (rho c^3)
 #pragma unroll
     for (int i = 0; i < 3; ++i) k.qh[i] = W[10 + i] * is3;
-    T Rh = W[13] / (s3 * k.c);
+    T Rh = W[13] * (is3 * ic);
     k.t1 = k.Ph[0] + k.Ph[3] + k.Ph[5];
     symsq(k.Ph, k.P2);
     k.t2 = k.P2[0] + k.P2[3] + k.P2[5];
@@ -331,7 +333,7 @@ struct Sys14 {
     }
     BYEC<T> g = byec(sw, Pdd);
     T pref = (a * sw + b) / (T(2) * sw);
-    T base = T(4) * sw * sw * g.Y + qt * qt / T(10);
+    T base = T(4) * sw * sw * g.Y + qt * qt * T(0.1);
     T zmax = qd + qt * alpha;
     T zmin = -qd + qt * alpha;
     T Lmax = pref * hyperbola(zmax, T(-0.8) * zmax * sw * g.C + base) + g.E;
@@ -373,7 +375,7 @@ struct Sys14 {
     const T* u = W + 1;
     const T* P = W + 4;
     const T* q = W + 10;
-    T p = (P[0] + P[3] + P[5]) / T(3);
+    T p = (P[0] + P[3] + P[5]) * T(1.0 / 3.0);
     T Pu[3];
     symv(P, u, Pu);
     T uPu = u[0] * Pu[0] + u[1] * Pu[1] + u[2] * Pu[2];
@@ -429,10 +431,13 @@ struct Sys5 {
 
   template <class T> MX_HD static void core(const T* W, T sigma_lim, Core<T>& k) {
     k.rho = W[0];
-    k.c = msqrt(W[2] / k.rho);
-    T s3 = k.rho * (k.c * k.c * k.c);
-    k.qh = W[3] / s3;
-    T rh = W[4] / (s3 * k.c);
+    T irho = T(1) / k.rho;
+    T ip = T(1) / W[2];
+    k.c = msqrt(W[2] * irho);
+    T ic = msqrt(k.rho * ip);
+    T is3 = irho * (ic * ic * ic);
+    k.qh = W[3] * is3;
+    T rh = W[4] * (is3 * ic);
     T A = T(3) - rh;
     T X = A * A + T(8) * k.qh * k.qh;
     k.sig = sigma_root(A, X, T(2) * k.qh * k.qh, T(4));

@@ -76,6 +76,10 @@ def oracle_cell_step(W, i, j, kw, dt, tau_ref, r=4):
 
 
 PERTURB = 4 * 2.220446049250313e-16   # 4 ulp relative
+# The spread is estimated from a few random perturbations; rounding inside the GPU path
+# (FMA contraction, reciprocal multiplies, device libm) perturbs intermediate values rather
+# than the input, so the bar allows an order of magnitude over the estimate.
+SPREAD_FACTOR = 10.0
 
 
 def oracle_with_spread(kw, W0, nsteps=None, dt=0.0, tau_ref=0.0, t_end=0.0, trials=3, seed=0,
@@ -101,7 +105,7 @@ def oracle_with_spread(kw, W0, nsteps=None, dt=0.0, tau_ref=0.0, t_end=0.0, tria
     return base, spread, t, n
 
 
-def within_spread(gpu, base, spread, rel_floor=1e-12, factor=2.0):
+def within_spread(gpu, base, spread, rel_floor=1e-12, factor=SPREAD_FACTOR):
     """Per cell and moment: |gpu - oracle| <= rel_floor * max|oracle_v| + factor * spread.
     Returns (ok, worst excess ratio, per-moment field-relative error)."""
     g = np.asarray(gpu, dtype=float).reshape(base.shape[0], -1)
@@ -115,7 +119,7 @@ def within_spread(gpu, base, spread, rel_floor=1e-12, factor=2.0):
     return bool(ratio.max() <= 1.0), float(ratio.max()), err
 
 
-def oracle_cells_1d(W, cells, kw, nsteps, dt, tau_ref, trials=2, seed=0):
+def oracle_cells_1d(W, cells, kw, nsteps, dt, tau_ref, trials=3, seed=0):
     """Oracle values after `nsteps` fixed-dt steps at selected cells of a long 1D field, each
     computed on the patch [i - 4 nsteps, i + 4 nsteps] (the dependency cone of SSP-RK2 with
     a two-cell stencil per stage); a patch side inside the domain gets transmissive ghosts,
@@ -148,9 +152,10 @@ def oracle_cells_1d(W, cells, kw, nsteps, dt, tau_ref, trials=2, seed=0):
     return np.array(vals).T, np.array(spreads).T
 
 
-def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=2, seed=0):
-    """Long runs: the oracle's result at t_end and its L1 spread per moment (largest
-    ||perturbed - base||_1 over +-4 ulp input perturbations)."""
+def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0):
+    """Long runs: the oracle's result at t_end, its L1 spread per moment (largest
+    ||perturbed - base||_1 over +-4 ulp input perturbations) and the largest change of the
+    step count under the same perturbations."""
     s = to_setup(kw)
     U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
     if s.dim == 1:
@@ -158,8 +163,10 @@ def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=2, seed=0):
     base, t, n = sc.run(U0, s, tau_ref, t_end=t_end)
     rng = np.random.default_rng(seed)
     spread = np.zeros(base.shape[0])
+    nspread = 0
     for _ in range(trials):
         Up = U0 * (1.0 + rng.choice([-1.0, 1.0], U0.shape) * PERTURB)
-        out, _, _ = sc.run(Up, s, tau_ref, t_end=t_end)
+        out, _, nk = sc.run(Up, s, tau_ref, t_end=t_end)
         spread = np.maximum(spread, np.abs(out - base).reshape(base.shape[0], -1).sum(1))
-    return base, spread, t, n
+        nspread = max(nspread, abs(nk - n))
+    return base, spread, t, n, nspread

@@ -540,3 +540,37 @@ def test_jet_inflow_ghost_rows_and_core_state():
     assert abs(Wj[13] / (p * p / Wj[0]) - 15.0) < 1e-13 and np.all(Wj[10:13] == 0)
     assert abs(math.hypot(Wj[1], Wj[2]) - 3 * math.sqrt(5 / 3)) < 1e-13
     assert Wj[2] > 0 and ghost[2, 307] < 0
+
+
+def test_baradaran_on_realizability_boundary_is_fastest_beam():
+    """On the realizability boundary (sigma = 1) a 1D1V distribution is two beams whose
+    dimensionless velocities solve x^2 = q* x + 1 (Section 2.3.1); the fastest signal is the
+    faster beam, (q* + sqrt(q*^2 + 4))/2, which Baradaran's estimate reproduces exactly
+    there (C = E = 0, B = Y = 1 at sigma = 1).  Checked through the oracle's full
+    dimensional path on genuine two-point distributions."""
+    rng = np.random.default_rng(77)
+    for _ in range(10):
+        w = rng.uniform(0.1, 1.0, 2)
+        v = rng.normal(0, 2, 2)
+        W, _ = kr.particle_state5(w, v)
+        lmin, lmax = ws.wavespeeds5(W[:, None], 1e-4)
+        # sigma = 1 up to rounding, and sqrt(10 - 16 sqrt(s) + 6 s) turns a 1e-16 error of
+        # sigma into ~1e-8: the bound reflects that slope, not a looser check of the form
+        assert abs(lmax[0] - v.max()) < 1e-6 * (abs(v).max() + 1)
+        assert abs(lmin[0] - v.min()) < 1e-6 * (abs(v).max() + 1)
+
+
+def test_14mom_wavespeed_large_heat_flux_asymptote():
+    """For large q*_x the hyperbola grows like 2 zeta, so sigma lambda*_max / zeta tends to
+    a sigma + b: the straight line in sigma the fit of Appendix B is built on.  For
+    q*_x -> -inf the cancellation-free branch tends to 0.2 (a sigma + b) C + E."""
+    for Pxx in (0.5, 1.0, 1.7):
+        a = 1.4 * Pxx**1.1 * math.exp(-Pxx**2)
+        b = 0.9 * Pxx * math.exp(-0.5 * Pxx**1.4)
+        for sig in (0.01, 0.3, 0.9):
+            q = 1e7
+            lam = ws.lam_max_star14(Pxx, q, 0.0, sig)
+            assert abs(sig * lam / q - (a * sig + b)) < 1e-6
+            C = math.sqrt((3 - 3 * sig) * Pxx)
+            lam_neg = ws.lam_max_star14(Pxx, -1e7, 0.0, sig)
+            assert abs(lam_neg - (0.2 * (a * sig + b) * C + 0.8 * C)) < 1e-6
