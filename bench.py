@@ -103,6 +103,9 @@ def main():
     ap.add_argument('--warmup', type=int, default=3)
     ap.add_argument('--n', type=int, default=N)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--precision', default='both', choices=('fp64', 'mixed', 'both'),
+                    help='fp64 (the headline value), mixed, or both (fp64 headline plus a mixed '
+                         'sub-record with its L1 deviation from the FP64 run)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a plain 2 GiB device copy (HBM counter calibration)')
     a = ap.parse_args()
@@ -126,25 +129,33 @@ def main():
         print(json.dumps({'copy_kernel_bytes_read': m * 8, 'copy_kernel_bytes_written': m * 8}))
         return
     n = a.n
-    kw = jets_kwargs(n)
     tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
     stream = torch.cuda.current_stream()
-    s = solver.MaxEntSolver(stream=stream, **kw)
-    s.init_state(inputs.crossed_jets_initial(n, n))
-    if a.warmup:
-        s.step(a.warmup, tau_ref=tau)
-    s.set_profiling(True)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    info = s.step(a.steps, tau_ref=tau)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    stage_ms, launches = s.profile()
-    s.close()
+    W0 = inputs.crossed_jets_initial(n, n)
 
+    def timed(precision):
+        kw = jets_kwargs(n)
+        kw['precision'] = precision
+        s = solver.MaxEntSolver(stream=stream, **kw)
+        s.init_state(W0)
+        if a.warmup:
+            s.step(a.warmup, tau_ref=tau)
+        s.set_profiling(True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        info = s.step(a.steps, tau_ref=tau)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        stage_ms, launches = s.profile()
+        U = s.get('conserved')
+        s.close()
+        return ms, stage_ms, launches, info, U
+
+    head = 'fp64' if a.precision in ('fp64', 'both') else 'mixed'
+    ms, stage_ms, launches, info, U_head = timed(head)
     cells = n * n
     cups = cells * a.steps / (ms / 1e3)
     avg_stage_ms = stage_ms / max(launches, 1)
@@ -153,7 +164,7 @@ def main():
     achieved = flops_per_launch / (avg_stage_ms / 1e3) / 1e12
     hbm_achieved = bytes_per_launch / (avg_stage_ms / 1e3) / 1e9
     out = {
-        'metric': 'cell-updates/s (14-moment 2D crossed jets, FP64)',
+        'metric': f'cell-updates/s (14-moment 2D crossed jets, {head.upper()})',
         'value': cups,
         'unit': 'cell-updates/s',
         'n_gpus': 1,
@@ -163,23 +174,38 @@ def main():
         'higher_is_better': True,
         'scaling': 'weak',
         'vs_baseline': None,
-        'dtype': 'f64',
+        'dtype': 'f64' if head == 'fp64' else 'f64 state + f32 closure/flux',
         'data': 'synthetic',
         'config': {'workload': f'2D crossed jets, 14-moment, {n}x{n}, MUSCL-minmod + HLL + '
                                f'SSP-RK2, CFL 0.4, Kn 0.1', 'cells': cells, 'precision': 'fp64',
-                   'steps_in_workload': 2000},
+                   'steps_in_workload': 2000, 'precision_mode': head},
         'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms / 1e3) / 1e9,
         'sim_time_reached': info['t'],
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VECTOR_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VECTOR_PEAK_TFLOPS,
                      'traffic': measured_traffic(),
-                     'kernel': 'stage_kernel<Sys14,2,2,16,15,256> (FP64)',
+                     'kernel': f'stage_kernel<Sys14,2,2,{0 if head == "fp64" else 1},16,15,256> ({head})',
                      'avg_launch_ms': avg_stage_ms, 'launches': launches,
                      'flops_per_launch': flops_per_launch,
                      'hbm_algorithmic_bytes_per_launch': bytes_per_launch,
                      'hbm_achieved_gbs': hbm_achieved,
                      'hbm_frac': hbm_achieved / HBM_PEAK_GBS},
     }
+    if a.precision == 'both':
+        ms_m, stage_ms_m, launches_m, info_m, U_m = timed('mixed')
+        d = (U_m - U_head).abs().reshape(14, -1).sum(1)
+        ref = U_head.abs().reshape(14, -1).sum(1).clamp_min(1e-300)
+        avg_m = stage_ms_m / max(launches_m, 1)
+        out['mixed'] = {
+            'value': cells * a.steps / (ms_m / 1e3), 'unit': 'cell-updates/s',
+            'ms_per_step': ms_m / a.steps, 'speedup_vs_fp64': ms / ms_m,
+            'avg_stage_launch_ms': avg_m,
+            'alu_tflops_algorithmic': flops_per_launch / (avg_m / 1e3) / 1e12,
+            'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms_m / 1e3) / 1e9,
+            'l1_rel_deviation_from_fp64_per_moment': [float(x) for x in (d / ref).cpu()],
+            'fp64_reevaluated_face_state_fraction':
+                info_m['n_fp64_states'] / max(info_m['n_face_states'], 1),
+        }
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()
     print(json.dumps(out), flush=True)

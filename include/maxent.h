@@ -47,7 +47,7 @@ typedef enum {
 
 enum { MAXENT_BC_TRANSMISSIVE = 0, MAXENT_BC_PERIODIC = 1, MAXENT_BC_REFLECTIVE = 2,
        MAXENT_BC_JET = 3 };
-enum { MAXENT_FP64 = 0 };
+enum { MAXENT_FP64 = 0, MAXENT_MIXED = 2 };
 enum { MAXENT_MINMOD = 0, MAXENT_VANALBADA = 1 };
 enum { MAXENT_HLL = 0, MAXENT_RUSANOV = 1 };
 enum { MAXENT_FE = 0, MAXENT_SSPRK2 = 1, MAXENT_MIDPOINT = 2 };
@@ -81,7 +81,12 @@ typedef struct {
 } maxent_problem;
 
 /* Numerics.
- *   precision     MAXENT_FP64.
+ *   precision     MAXENT_FP64, or MAXENT_MIXED: state, primitive recovery, reconstruction,
+ *                 HLL dissipation and update in FP64; closure, wave speeds and physical
+ *                 fluxes of each face state in FP32 (the dimensionless closure is robust in
+ *                 single precision, Section 3.3), re-evaluated in FP64 near the Junk
+ *                 subspace (A < -1e-3, sigma < 1e-2) and the realizability boundary
+ *                 (sigma > 0.999).
  *   order         1 (first order, cell states at faces) or 2 (MUSCL on primitives with one
  *                 common, most stringent limiter factor, Section 3.2).
  *   limiter       MINMOD or VANALBADA (the paper's choice).
@@ -111,6 +116,8 @@ typedef struct {
   long long n_fallback;     /* positivity fallbacks since init_state                 */
   int fail_step;            /* first failing step index (1-based), 0 if none         */
   int fail_code;            /* bit 1: non-finite, bit 2: rho <= 0 / P not SPD        */
+  long long n_fp64_states;  /* MIXED: face states re-evaluated in FP64 since init    */
+  long long n_face_states;  /* MIXED: face states evaluated since init (tile faces)  */
 } maxent_info;
 
 /* Allocate a solver.  `stream` is a hipStream_t (NULL for the default stream).
@@ -148,6 +155,62 @@ int maxent_get_moments(maxent_solver* s, int repr, double* dst, int dst_on_devic
 /* Number of components (5 or 14), time and step count of a solver. */
 int maxent_num_vars(const maxent_solver* s);
 int maxent_get_info(maxent_solver* s, maxent_info* info);
+
+/* ------------------------------------------------------------------ batched 1D tubes
+ * Many independent 1D 14-moment problems of uneven length advance together: each instance
+ * has its own grid, collision time, end time and CFL time step.  The common settings come
+ * from `common` (bc[0], bc[1], tau_mode, rho_ref, T_ref; other fields ignored) and
+ * `numerics` (order 2, SSPRK2 or MIDPOINT, FP64 or MIXED).  The state is the concatenation
+ * of the instances' fields: init_state / get_moments take [14][total cells] with instance
+ * i occupying cells [sum_{k<i} n_k, sum_{k<=i} n_k).  tau_ref <= 0 makes an instance
+ * collisionless. */
+typedef struct {
+  double x0, x1;            /* the instance's domain                                  */
+  double tau_ref;           /* BGK reference collision time (<= 0: collisionless)     */
+  double t_end;             /* > 0: the instance stops there                          */
+  int n_cells;              /* >= 4                                                   */
+  int pad;
+} maxent_instance;
+
+typedef struct {
+  double t, dt_last;
+  long long steps;
+  int fail_step;            /* first failing step of this instance, 0 if none         */
+  int fail_code;
+} maxent_instance_info;
+
+typedef struct {
+  long long max_steps;      /* steps of the longest-running instance so far           */
+  long long cell_updates;   /* sum over instances of cells x steps                    */
+  long long n_active;       /* instances that have not reached t_end                  */
+  long long n_fallback, n_fp64_states, n_face_states;
+  int fail_step, fail_code;
+} maxent_batch_info;
+
+/* Errors: INVAL (system != 14, order != 2, FE integrator, an instance with < 4 cells, x1 <= x0,
+ * t_end <= 0), NOMEM, DEVICE. */
+int maxent_create_batch(const maxent_problem* common, const maxent_numerics* numerics,
+                        int n_inst, const maxent_instance* instances, void* stream,
+                        maxent_solver** out);
+
+/* Advance every instance until it reaches its t_end, or at most about max_steps steps.
+ * Steps are replayed in chunks of `chunk` steps captured once as a HIP graph (on an internal
+ * stream of default priority, ordered after earlier work on the solver's stream); after each
+ * chunk one word is read to see whether any instance is still active.  per_inst may be NULL
+ * or hold n_inst records.  A failing instance stops (later steps are no-ops for it). */
+int maxent_step_batch(maxent_solver* s, int max_steps, int chunk, maxent_batch_info* info,
+                      maxent_instance_info* per_inst);
+
+/* Launch shape of the batched stage kernels: threads per workgroup (64, 128 or 256; a tile
+ * holds threads - 1 cells) and persistent workgroups per compute unit (1..32). */
+int maxent_set_batch_launch(maxent_solver* s, int threads, int wg_per_cu);
+int maxent_get_batch_launch(maxent_solver* s, int* threads, int* wg_per_cu);
+
+/* Autotuner: time trial_steps steps of each launch shape (threads 64/128/256 x workgroups
+ * per CU 2/4/8/16) from the current state, restoring the state after every trial, and keep
+ * the fastest.  Outputs may be NULL. */
+int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* wg_per_cu,
+                          double* best_cell_updates_per_s);
 
 /* Optional timing of the fused stage kernels: when enabled, every stage-kernel launch of
  * maxent_step is bracketed by HIP events on the solver's stream and the elapsed times are

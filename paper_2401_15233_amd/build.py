@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libmaxent.so')
-SOURCES = ['mx_api.hip', 'mx_kernels.hip']
+SOURCES = ['mx_api.hip', 'mx_kernels.hip', 'mx_batch.hip']
 ARCH = os.environ.get('MAXENT_OFFLOAD_ARCH', 'gfx950')
 
 
@@ -27,6 +27,9 @@ def flags():
             # packed FP32 instructions are disabled for all device code of this library
             '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
             '-munsafe-fp-atomics', '-Wno-unused-command-line-argument',
+            # single-precision division and square root of the mixed-precision path need
+            # not be correctly rounded (about 1 ulp is enough there)
+            '-fno-hip-fp32-correctly-rounded-divide-sqrt',
             f'-I{os.path.join(ROOT, "include")}', f'-I{CSRC}']
 
 

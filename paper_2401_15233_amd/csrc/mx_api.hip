@@ -8,8 +8,31 @@
 
 #include "../../include/maxent.h"
 #include "mx_internal.hpp"
+#include "mx_batch.hpp"
 
 using mx::DevCtrl;
+
+// batched 1D tubes: per-instance records, static tile lists per tile width, graph of a chunk
+struct BatchState {
+  int n_inst = 0;
+  long long total = 0;
+  std::vector<mx::BatchInst> init;       // records as created (t = 0)
+  mx::BatchInst* d_inst = nullptr;
+  mx::BatchInst* h_inst = nullptr;       // pinned read-back
+  mx::BatchCtrl* d_ctrl = nullptr;
+  mx::BatchCtrl* h_ctrl = nullptr;       // pinned read-back
+  int2* d_tiles[3] = {nullptr, nullptr, nullptr};   // tile widths 63, 127, 255
+  int n_tiles[3] = {0, 0, 0};
+  int* d_cell_inst = nullptr;
+  int nt = 64;                           // threads per workgroup = tile width + 1
+  int wg_per_cu = 4;
+  int n_cu = 256;
+  hipStream_t gstream = nullptr;         // capture stream (a captured graph cannot use the null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_chunk = 0;
+  bool graph_valid = false;
+};
 
 struct maxent_solver {
   maxent_problem prob;
@@ -32,6 +55,7 @@ struct maxent_solver {
   size_t ev_used = 0;
   double prof_ms = 0.0;
   long long prof_n = 0;
+  BatchState* batch = nullptr;
   std::string err;
 };
 
@@ -77,7 +101,7 @@ static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
   }
   if (p.tau_mode != MAXENT_TAU_LOCAL && p.tau_mode != MAXENT_TAU_CONST) return "bad tau_mode";
   if (p.tau_mode == MAXENT_TAU_LOCAL && !(p.rho_ref > 0 && p.T_ref > 0)) return "bad rho_ref/T_ref";
-  if (n.precision != MAXENT_FP64) return "unsupported precision";
+  if (n.precision != MAXENT_FP64 && n.precision != MAXENT_MIXED) return "unsupported precision";
   if (n.order != 1 && n.order != 2) return "order must be 1 or 2";
   if (n.limiter != MAXENT_MINMOD && n.limiter != MAXENT_VANALBADA) return "bad limiter";
   if (n.flux != MAXENT_HLL && n.flux != MAXENT_RUSANOV) return "bad flux";
@@ -105,6 +129,20 @@ extern "C" void maxent_destroy(maxent_solver* s) {
   if (s->ctrl) (void)hipFree(s->ctrl);
   if (s->ctrl_host) (void)hipHostFree(s->ctrl_host);
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  if (BatchState* b = s->batch) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->gstream) (void)hipStreamDestroy(b->gstream);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->h_inst) (void)hipHostFree(b->h_inst);
+    if (b->d_ctrl) (void)hipFree(b->d_ctrl);
+    if (b->h_ctrl) (void)hipHostFree(b->h_ctrl);
+    for (int k = 0; k < 3; ++k)
+      if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
+    if (b->d_cell_inst) (void)hipFree(b->d_cell_inst);
+    delete b;
+  }
   delete s;
 }
 
@@ -172,7 +210,8 @@ static mx::StageParams stage_params(maxent_solver* s, double tau_ref) {
 }
 
 static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::StageParams& p) {
-  if (!s->prof) return mx::launch_stage(sys, dim, ord, p, s->stream);
+  const int prec = s->num.precision == MAXENT_MIXED ? 1 : 0;
+  if (!s->prof) return mx::launch_stage(sys, dim, ord, prec, p, s->stream);
   while (s->ev.size() < s->ev_used + 2) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
@@ -180,7 +219,7 @@ static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::S
     s->ev.push_back(e);
   }
   hipError_t r = hipEventRecord(s->ev[s->ev_used], s->stream);
-  if (r == hipSuccess) r = mx::launch_stage(sys, dim, ord, p, s->stream);
+  if (r == hipSuccess) r = mx::launch_stage(sys, dim, ord, prec, p, s->stream);
   if (r == hipSuccess) r = hipEventRecord(s->ev[s->ev_used + 1], s->stream);
   s->ev_used += 2;
   return r;
@@ -222,6 +261,43 @@ static void fill_info(maxent_solver* s, maxent_info* info) {
   info->n_fallback = c.n_fallback;
   info->fail_step = (c.fail_step == 0x7fffffff) ? 0 : c.fail_step;
   info->fail_code = c.status;
+  info->n_fp64_states = c.n_fp64;
+  info->n_face_states = c.n_states;
+}
+
+static mx::BatchParams batch_params(maxent_solver* s) {
+  BatchState* b = s->batch;
+  mx::BatchParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.plane = s->plane;
+  p.inst = b->d_inst;
+  int k = b->nt == 64 ? 0 : (b->nt == 128 ? 1 : 2);
+  p.tiles = b->d_tiles[k];
+  p.n_tiles = b->n_tiles[k];
+  p.cell_inst = b->d_cell_inst;
+  p.bc_lo = s->prob.bc[0];
+  p.bc_hi = s->prob.bc[1];
+  p.tau_mode = s->prob.tau_mode;
+  p.rho_ref = s->prob.rho_ref;
+  p.T_ref = s->prob.T_ref;
+  p.sigma_lim = s->num.sigma_lim;
+  p.kws = s->num.k_ws;
+  p.limiter = s->num.limiter;
+  p.flux = s->num.flux;
+  p.fallback = s->num.positivity_fallback;
+  p.ctrl = s->ctrl;
+  return p;
+}
+
+// restore the per-instance records to t = 0 and reduce each instance's first CFL rate
+static int batch_reset(maxent_solver* s) {
+  BatchState* b = s->batch;
+  HIP_TRY(s, hipMemcpyAsync(b->d_inst, b->init.data(), b->init.size() * sizeof(mx::BatchInst),
+                            hipMemcpyHostToDevice, s->stream));
+  mx::BatchParams p = batch_params(s);
+  p.Ub = s->U;
+  HIP_TRY(s, mx::launch_batch_cfl(p, b->total, s->stream));
+  return MAXENT_OK;
 }
 
 extern "C" int maxent_init_state(maxent_solver* s, int repr, const double* src, int src_on_device,
@@ -237,7 +313,12 @@ extern "C" int maxent_init_state(maxent_solver* s, int repr, const double* src, 
   HIP_TRY(s, mx::launch_ctrl_reset(s->ctrl, t0, s->stream));
   HIP_TRY(s, mx::launch_ingest(s->prob.system, repr, s->stage, s->U, s->prob.nx, s->prob.ny,
                                s->pitch, s->ctrl, s->stream));
-  HIP_TRY(s, run_cfl(s));
+  if (s->batch) {
+    int rc = batch_reset(s);
+    if (rc) return rc;
+  } else {
+    HIP_TRY(s, run_cfl(s));
+  }
   int rc = read_ctrl(s);
   if (rc) return rc;
   s->ready = true;
@@ -246,7 +327,7 @@ extern "C" int maxent_init_state(maxent_solver* s, int repr, const double* src, 
   if (st) {
     // keep the loaded state but clear the status so that the caller may inspect it
     HIP_TRY(s, mx::launch_ctrl_reset(s->ctrl, t0, s->stream));
-    HIP_TRY(s, run_cfl(s));
+    if (!s->batch) HIP_TRY(s, run_cfl(s));
     s->ready = false;
     if (st & mx::ST_NONFINITE) return fail(s, MAXENT_E_NONFINITE, "initial state has non-finite values");
     return fail(s, MAXENT_E_UNREALIZABLE, "initial state has rho <= 0 or a non-SPD pressure tensor");
@@ -262,6 +343,7 @@ extern "C" int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, d
   if (std::isnan(tau_ref)) return fail(s, MAXENT_E_INVAL, "tau_ref is NaN");
   if (std::isnan(t_end)) return fail(s, MAXENT_E_INVAL, "t_end is NaN");
   if (!s->ready) return fail(s, MAXENT_E_STATE, "step before a valid init_state");
+  if (s->batch) return fail(s, MAXENT_E_STATE, "a batch solver advances with maxent_step_batch");
   const bool cfl_mode = !(dt > 0);
   mx::StageParams p = stage_params(s, tau_ref);
   const int sys = s->prob.system, dim = s->prob.dim, ord = s->num.order;
@@ -337,5 +419,276 @@ extern "C" int maxent_get_profile(maxent_solver* s, double* stage_ms_total, long
   if (!s || !stage_ms_total || !stage_launches) return MAXENT_E_INVAL;
   *stage_ms_total = s->prof_ms;
   *stage_launches = s->prof_n;
+  return MAXENT_OK;
+}
+
+// ------------------------------------------------------------------------- batched tubes
+extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_numerics* num,
+                                   int n_inst, const maxent_instance* inst, void* stream,
+                                   maxent_solver** out) {
+  if (!common || !num || !inst || !out) return fail(nullptr, MAXENT_E_INVAL, "null argument");
+  *out = nullptr;
+  if (common->system != 14) return fail(nullptr, MAXENT_E_INVAL, "batched tubes use the 14-moment system");
+  if (n_inst < 1 || n_inst > 65536) return fail(nullptr, MAXENT_E_INVAL, "n_inst must be 1..65536");
+  if (num->order != 2) return fail(nullptr, MAXENT_E_INVAL, "batched tubes use the second-order scheme");
+  if (num->integrator != MAXENT_SSPRK2 && num->integrator != MAXENT_MIDPOINT)
+    return fail(nullptr, MAXENT_E_INVAL, "batched tubes use SSPRK2 or MIDPOINT");
+  long long total = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    if (inst[i].n_cells < 4) return fail(nullptr, MAXENT_E_INVAL, "every instance needs >= 4 cells");
+    if (!(inst[i].x1 > inst[i].x0)) return fail(nullptr, MAXENT_E_INVAL, "instance x1 must exceed x0");
+    if (!(inst[i].t_end > 0)) return fail(nullptr, MAXENT_E_INVAL, "instance t_end must be > 0");
+    if (std::isnan(inst[i].tau_ref)) return fail(nullptr, MAXENT_E_INVAL, "instance tau_ref is NaN");
+    total += inst[i].n_cells;
+  }
+  if (total > (1ll << 31)) return fail(nullptr, MAXENT_E_INVAL, "too many cells");
+  maxent_problem p = *common;
+  p.dim = 1;
+  p.nx = (int)total;
+  p.ny = 1;
+  p.x0 = 0.0;
+  p.x1 = 1.0;
+  p.bc[2] = p.bc[3] = MAXENT_BC_TRANSMISSIVE;
+  if (p.bc[0] == MAXENT_BC_JET || p.bc[1] == MAXENT_BC_JET) return fail(nullptr, MAXENT_E_INVAL, "no jet inflow in 1D");
+  maxent_solver* s = nullptr;
+  int rc = maxent_create(&p, num, stream, &s);
+  if (rc) return rc;
+  BatchState* b = new (std::nothrow) BatchState();
+  if (!b) { maxent_destroy(s); return fail(nullptr, MAXENT_E_NOMEM, "host allocation failed"); }
+  s->batch = b;
+  b->n_inst = n_inst;
+  b->total = total;
+  b->init.resize(n_inst);
+  std::vector<int> cell_inst(total);
+  std::vector<int2> tiles[3];
+  long long off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    mx::BatchInst r;
+    std::memset(&r, 0, sizeof(r));
+    r.t_end = inst[i].t_end;
+    r.dx = (inst[i].x1 - inst[i].x0) / inst[i].n_cells;
+    r.inv_dx = 1.0 / r.dx;
+    r.tau_ref = inst[i].tau_ref;
+    r.off = off;
+    r.n = inst[i].n_cells;
+    r.fail_step = 0x7fffffff;
+    b->init[i] = r;
+    for (int c = 0; c < r.n; ++c) cell_inst[off + c] = i;
+    const int widths[3] = {63, 127, 255};
+    for (int k = 0; k < 3; ++k)
+      for (int st = 0; st < r.n; st += widths[k]) tiles[k].push_back(make_int2(i, st));
+    off += r.n;
+  }
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, s->device);
+  if (e == hipSuccess) b->n_cu = prop.multiProcessorCount;
+  if (e == hipSuccess) e = hipMalloc(&b->d_inst, n_inst * sizeof(mx::BatchInst));
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_inst, n_inst * sizeof(mx::BatchInst));
+  if (e == hipSuccess) e = hipMalloc(&b->d_ctrl, sizeof(mx::BatchCtrl));
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_ctrl, sizeof(mx::BatchCtrl));
+  if (e == hipSuccess) e = hipMalloc(&b->d_cell_inst, total * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(b->d_cell_inst, cell_inst.data(), total * sizeof(int), hipMemcpyHostToDevice);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    b->n_tiles[k] = (int)tiles[k].size();
+    e = hipMalloc(&b->d_tiles[k], tiles[k].size() * sizeof(int2));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_tiles[k], tiles[k].data(), tiles[k].size() * sizeof(int2), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(b->d_inst, b->init.data(), n_inst * sizeof(mx::BatchInst), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    std::string m = std::string("batch allocation failed: ") + hipGetErrorString(e);
+    maxent_destroy(s);
+    return fail(nullptr, e == hipErrorOutOfMemory ? MAXENT_E_NOMEM : MAXENT_E_DEVICE, m);
+  }
+  *out = s;
+  return MAXENT_OK;
+}
+
+// enqueue `steps` batched steps on stream st
+static hipError_t batch_enqueue(maxent_solver* s, int steps, hipStream_t st) {
+  BatchState* b = s->batch;
+  mx::BatchParams p = batch_params(s);
+  const int grid = b->wg_per_cu * b->n_cu;
+  const bool mid = s->num.integrator == MAXENT_MIDPOINT;
+  const int prec = s->num.precision == MAXENT_MIXED ? 1 : 0;
+  for (int k = 0; k < steps; ++k) {
+    hipError_t e = mx::launch_batch_finalize(b->d_inst, b->n_inst, s->num.cfl, b->d_ctrl, st);
+    if (e != hipSuccess) return e;
+    p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
+    p.mode = mx::MODE_EULER; p.cdt = mid ? 0.5 : 1.0; p.do_cfl = 0;
+    e = mx::launch_batch_stage(prec, b->nt, p, grid, st);
+    if (e != hipSuccess) return e;
+    p.Ub = s->Us; p.Ua = s->U; p.Uout = s->U;
+    p.mode = mid ? mx::MODE_MID2 : mx::MODE_HEUN2; p.cdt = 1.0; p.do_cfl = 1;
+    e = mx::launch_batch_stage(prec, b->nt, p, grid, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static int batch_capture(maxent_solver* s, int chunk) {
+  BatchState* b = s->batch;
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  b->graph_valid = false;
+  hipGraph_t g = nullptr;
+  HIP_TRY(s, hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = batch_enqueue(s, chunk, b->gstream);
+  hipError_t e2 = hipStreamEndCapture(b->gstream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(s, MAXENT_E_DEVICE, std::string("graph capture failed: ") +
+                                        hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(s, MAXENT_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  b->graph_chunk = chunk;
+  b->graph_valid = true;
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_step_batch(maxent_solver* s, int max_steps, int chunk, maxent_batch_info* info,
+                                 maxent_instance_info* per_inst) {
+  if (!s) return MAXENT_E_INVAL;
+  if (!s->batch) return fail(s, MAXENT_E_STATE, "not a batch solver (maxent_create_batch)");
+  if (!s->ready) return fail(s, MAXENT_E_STATE, "step before a valid init_state");
+  if (max_steps < 0 || chunk < 1 || chunk > 100000) return fail(s, MAXENT_E_INVAL, "bad max_steps or chunk");
+  BatchState* b = s->batch;
+  if (!b->graph_valid || b->graph_chunk != chunk) {
+    int rc = batch_capture(s, chunk);
+    if (rc) return rc;
+  }
+  // order the graph replays after earlier work on the caller's stream, and back
+  HIP_TRY(s, hipEventRecord(b->ev_in, s->stream));
+  HIP_TRY(s, hipStreamWaitEvent(b->gstream, b->ev_in, 0));
+  int done = 0;
+  while (done < max_steps) {
+    HIP_TRY(s, hipGraphLaunch(b->exec, b->gstream));
+    done += chunk;
+    HIP_TRY(s, hipMemcpyAsync(b->h_ctrl, b->d_ctrl, sizeof(mx::BatchCtrl), hipMemcpyDeviceToHost, b->gstream));
+    HIP_TRY(s, hipStreamSynchronize(b->gstream));
+    if (b->h_ctrl->n_active == 0) break;
+  }
+  HIP_TRY(s, hipEventRecord(b->ev_out, b->gstream));
+  HIP_TRY(s, hipStreamWaitEvent(s->stream, b->ev_out, 0));
+  HIP_TRY(s, hipMemcpyAsync(b->h_inst, b->d_inst, b->n_inst * sizeof(mx::BatchInst), hipMemcpyDeviceToHost,
+                            s->stream));
+  int rc = read_ctrl(s);
+  if (rc) return rc;
+  long long max_steps_taken = 0, cell_updates = 0, active = 0;
+  int status = 0, first_fail = 0x7fffffff;
+  for (int i = 0; i < b->n_inst; ++i) {
+    const mx::BatchInst& r = b->h_inst[i];
+    if (r.step > max_steps_taken) max_steps_taken = r.step;
+    cell_updates += r.step * (long long)r.n;
+    if (r.t < r.t_end * (1.0 - 1e-14) && r.status == 0) ++active;
+    status |= r.status;
+    if (r.status && r.fail_step < first_fail) first_fail = r.fail_step;
+    if (per_inst) {
+      per_inst[i].t = r.t;
+      per_inst[i].dt_last = r.dt_last;
+      per_inst[i].steps = r.step;
+      per_inst[i].fail_step = r.fail_step == 0x7fffffff ? 0 : r.fail_step;
+      per_inst[i].fail_code = r.status;
+    }
+  }
+  if (info) {
+    info->max_steps = max_steps_taken;
+    info->cell_updates = cell_updates;
+    info->n_active = active;
+    info->n_fallback = s->ctrl_host->n_fallback;
+    info->n_fp64_states = s->ctrl_host->n_fp64;
+    info->n_face_states = s->ctrl_host->n_states;
+    info->fail_code = status;
+    info->fail_step = status ? first_fail : 0;
+  }
+  if (status & mx::ST_NONFINITE) return fail(s, MAXENT_E_NONFINITE, "non-finite cell state in an instance");
+  if (status & mx::ST_UNREALIZABLE) return fail(s, MAXENT_E_UNREALIZABLE, "rho <= 0 or P not SPD in an instance");
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_set_batch_launch(maxent_solver* s, int threads, int wg_per_cu) {
+  if (!s || !s->batch) return MAXENT_E_INVAL;
+  if (threads != 64 && threads != 128 && threads != 256) return fail(s, MAXENT_E_INVAL, "threads must be 64, 128 or 256");
+  if (wg_per_cu < 1 || wg_per_cu > 32) return fail(s, MAXENT_E_INVAL, "wg_per_cu must be 1..32");
+  s->batch->nt = threads;
+  s->batch->wg_per_cu = wg_per_cu;
+  s->batch->graph_valid = false;
+  return MAXENT_OK;
+}
+
+extern "C" int maxent_get_batch_launch(maxent_solver* s, int* threads, int* wg_per_cu) {
+  if (!s || !s->batch || !threads || !wg_per_cu) return MAXENT_E_INVAL;
+  *threads = s->batch->nt;
+  *wg_per_cu = s->batch->wg_per_cu;
+  return MAXENT_OK;
+}
+
+// Time `trial_steps` steps of every launch shape from the current state and keep the fastest
+// (cell-updates per second).  The state and the per-instance records are restored after each
+// trial, so the call leaves the solution untouched.
+extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* wg_per_cu,
+                                     double* best_rate) {
+  if (!s || !s->batch) return MAXENT_E_INVAL;
+  if (!s->ready) return fail(s, MAXENT_E_STATE, "autotune before a valid init_state");
+  if (trial_steps < 1 || trial_steps > 10000) return fail(s, MAXENT_E_INVAL, "trial_steps must be 1..10000");
+  BatchState* b = s->batch;
+  size_t field = (size_t)s->nv * s->plane * sizeof(double);
+  size_t recs = b->n_inst * sizeof(mx::BatchInst);
+  double* saveU = nullptr;
+  mx::BatchInst* saveI = nullptr;
+  HIP_TRY(s, hipMalloc(&saveU, field));
+  hipError_t e = hipMalloc(&saveI, recs);
+  if (e != hipSuccess) { (void)hipFree(saveU); return fail(s, MAXENT_E_NOMEM, "autotune snapshot"); }
+  e = hipMemcpyAsync(saveU, s->U, field, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(saveI, b->d_inst, recs, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  const int nts[3] = {64, 128, 256};
+  const int wgs[4] = {2, 4, 8, 16};
+  double best = -1.0;
+  int bt = b->nt, bw = b->wg_per_cu;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+    for (int w = 0; w < 4 && e == hipSuccess; ++w) {
+      b->nt = nts[a];
+      b->wg_per_cu = wgs[w];
+      e = batch_enqueue(s, 1, s->stream);  // warm-up step (first use of the shape)
+      if (e == hipSuccess) e = hipMemcpyAsync(s->U, saveU, field, hipMemcpyDeviceToDevice, s->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, saveI, recs, hipMemcpyDeviceToDevice, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+      if (e == hipSuccess) e = batch_enqueue(s, trial_steps, s->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(b->h_inst, b->d_inst, recs, hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      long long cu = 0;
+      for (int i = 0; i < b->n_inst; ++i) cu += b->h_inst[i].step * (long long)b->h_inst[i].n;
+      double rate = ms > 0 ? cu / (ms * 1e-3) : 0.0;
+      if (rate > best) { best = rate; bt = nts[a]; bw = wgs[w]; }
+      e = hipMemcpyAsync(s->U, saveU, field, hipMemcpyDeviceToDevice, s->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, saveI, recs, hipMemcpyDeviceToDevice, s->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(saveU);
+  (void)hipFree(saveI);
+  if (e != hipSuccess) return fail(s, MAXENT_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  b->nt = bt;
+  b->wg_per_cu = bw;
+  b->graph_valid = false;
+  // counters polluted by the trials
+  HIP_TRY(s, mx::launch_ctrl_reset(s->ctrl, 0.0, s->stream));
+  if (threads) *threads = bt;
+  if (wg_per_cu) *wg_per_cu = bw;
+  if (best_rate) *best_rate = best;
   return MAXENT_OK;
 }

@@ -1,0 +1,48 @@
+// Device records and launchers of the batched 1D shock tubes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mx_internal.hpp"
+
+namespace mx {
+
+struct BatchInst {
+  double dt, t, t_end, dt_last;
+  double dx, inv_dx, tau_ref;
+  unsigned long long maxrate;    // bit pattern of the max CFL rate (positive double)
+  long long step;
+  long long off;                 // first cell in the concatenated field
+  int n;                         // cells
+  int status;                    // bit 1 non-finite, bit 2 unrealizable
+  int fail_step;
+  int pad;
+};
+
+struct BatchCtrl {
+  int n_active;                  // instances that advanced in the last finalize
+};
+
+struct BatchParams {
+  const double* Ub;
+  const double* Ua;
+  double* Uout;
+  long long plane;               // padded total cells
+  BatchInst* inst;
+  const int2* tiles;             // (instance, first local cell) of every tile
+  int n_tiles;
+  const int* cell_inst;          // instance of every cell (CFL initialisation)
+  int bc_lo, bc_hi;
+  int tau_mode;
+  double rho_ref, T_ref;
+  double sigma_lim, kws;
+  int limiter, flux, fallback;
+  int mode;
+  double cdt;
+  int do_cfl;
+  DevCtrl* ctrl;                 // shared counters (fallbacks, FP64 re-evaluations)
+};
+
+hipError_t launch_batch_stage(int precision, int nt, const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_finalize(BatchInst* in, int n_inst, double cfl, BatchCtrl* bc, hipStream_t s);
+hipError_t launch_batch_cfl(const BatchParams& p, long long total, hipStream_t s);
+
+}  // namespace mx

@@ -17,6 +17,8 @@ struct DevCtrl {
   long long n_fallback;          // positivity fallbacks
   int status;                    // bit 1 non-finite, bit 2 unrealizable
   int fail_step;                 // first failing step (0: none)
+  long long n_fp64;              // mixed precision: face states re-evaluated in FP64
+  long long n_states;            // mixed precision: face states evaluated
 };
 
 enum { MODE_EULER = 0, MODE_HEUN2 = 1, MODE_MID2 = 2 };
@@ -56,7 +58,8 @@ struct CflParams {
 };
 
 // launchers (mx_kernels.hip)
-hipError_t launch_stage(int system, int dim, int order, const StageParams& p, hipStream_t s);
+hipError_t launch_stage(int system, int dim, int order, int precision, const StageParams& p,
+                        hipStream_t s);
 hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s);
 hipError_t launch_finalize(DevCtrl* c, int dim, double cfl, double dx, hipStream_t s);
 hipError_t launch_ctrl_set(DevCtrl* c, double dt_fixed, double t_end, hipStream_t s);

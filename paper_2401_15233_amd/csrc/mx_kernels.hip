@@ -95,7 +95,7 @@ __device__ __forceinline__ void load_prims(const StageParams& p, const double* U
 }
 
 // ------------------------------------------------------------------ stage kernel
-template <class SYS, int DIM, int ORDER, int TX, int TY, int NT>
+template <class SYS, int DIM, int ORDER, int PREC, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   constexpr int NV = SYS::NV;
   constexpr int G = (ORDER == 2) ? 2 : 1;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   __shared__ double sPx[NPX];
   __shared__ double sPy[NPY];
   __shared__ double sRed[NT / 64];
-  __shared__ int sFlag[2];
+  __shared__ int sFlag[3];
 
   // XCD-aware tile order: hardware deals consecutive workgroups round-robin to the 8
   // XCDs; give each XCD a contiguous band of tiles so halos are shared in its L2.
@@ -138,7 +138,9 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
     }
     return;
   }
-  if (t < 2) sFlag[t] = 0;
+  if (t < 3) sFlag[t] = 0;
+  int n64 = 0;      // FP64 re-evaluations of face states (mixed precision)
+  int nstates = 0;  // face states evaluated
 
   // 1. tile + halo -> primitives in LDS
   for (int c = t; c < NL; c += NT) {
@@ -213,7 +215,9 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       lds(fi - 1, fj, WL); lds(fi, fj, WR);
     }
     double Fh[NV];
-    face_flux<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh);
+    if constexpr (PREC == 0) face_flux<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh);
+    else face_flux_mixed<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh, n64);
+    nstates += 2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
   }
@@ -234,7 +238,11 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       } else {
         lds(fi, fj - 1, WL); lds(fi, fj, WR);
       }
-      if constexpr (SYS::NV == 14) face_flux<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
+      if constexpr (SYS::NV == 14) {
+        if constexpr (PREC == 0) face_flux<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
+        else face_flux_mixed<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy, n64);
+      }
+      nstates += 2;
     }
   }
   __syncthreads();
@@ -302,10 +310,13 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   // block reductions: status, fallback count, CFL rate
   flag = wave_or(flag);
   nfb = wave_sum(nfb);
+  if constexpr (PREC != 0) n64 = wave_sum(n64);
+  nstates = wave_sum(nstates);
   const int lane = t & 63, wid = t >> 6;
   if (lane == 0) {
     if (flag) atomicOr(&sFlag[0], flag);
     if (nfb) atomicAdd(&sFlag[1], nfb);
+    if (PREC != 0 && n64) atomicAdd(&sFlag[2], n64);
   }
   if (p.do_cfl) {
     rate = wave_max(rate);
@@ -318,6 +329,11 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       atomicMin(&p.ctrl->fail_step, (int)p.ctrl->step);
     }
     if (sFlag[1]) atomicAdd((unsigned long long*)&p.ctrl->n_fallback, (unsigned long long)sFlag[1]);
+    if (PREC != 0) {
+      if (sFlag[2]) atomicAdd((unsigned long long*)&p.ctrl->n_fp64, (unsigned long long)sFlag[2]);
+      atomicAdd((unsigned long long*)&p.ctrl->n_states,
+                (unsigned long long)(2 * (NFX + NFY)));
+    }
     if (p.do_cfl) {
       double m = sRed[0];
       for (int k = 1; k < NT / 64; ++k) m = fmax(m, sRed[k]);
@@ -393,6 +409,7 @@ __global__ void ctrl_reset_kernel(DevCtrl* c, double t0) {
   if (threadIdx.x == 0) {
     c->dt = 0.0; c->t = t0; c->t_end = 0.0; c->dt_fixed = 0.0; c->dt_last = 0.0;
     c->maxrate = 0ull; c->step = 0; c->n_fallback = 0; c->status = 0; c->fail_step = 0x7fffffff;
+    c->n_fp64 = 0; c->n_states = 0;
   }
 }
 
@@ -459,29 +476,32 @@ __global__ void egress_kernel(int repr, const double* U, double* dst, int nx, in
 }
 
 // ------------------------------------------------------------------ launchers
-template <class SYS, int DIM, int ORDER>
+template <class SYS, int DIM, int ORDER, int PREC>
 static hipError_t launch_stage_t(const StageParams& p, hipStream_t s) {
+  int grid = ((p.nblk + 7) / 8) * 8;
   if constexpr (DIM == 2) {
-    constexpr int TX = 16, TY = 15, NT = 256;
-    int nb = p.nblk;
-    int grid = ((nb + 7) / 8) * 8;
-    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, TX, TY, NT>), dim3(grid), dim3(NT), 0, s, p);
+    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, PREC, 16, 15, 256>), dim3(grid), dim3(256), 0, s, p);
   } else {
-    constexpr int TX = 63, TY = 1, NT = 64;
-    int nb = p.nblk;
-    int grid = ((nb + 7) / 8) * 8;
-    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, TX, TY, NT>), dim3(grid), dim3(NT), 0, s, p);
+    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, PREC, 63, 1, 64>), dim3(grid), dim3(64), 0, s, p);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_stage(int system, int dim, int order, const StageParams& p, hipStream_t s) {
+template <int PREC>
+static hipError_t launch_stage_p(int system, int dim, int order, const StageParams& p, hipStream_t s) {
   if (system == 5) {
     if (dim != 1) return hipErrorInvalidValue;
-    return order == 2 ? launch_stage_t<Sys5, 1, 2>(p, s) : launch_stage_t<Sys5, 1, 1>(p, s);
+    return order == 2 ? launch_stage_t<Sys5, 1, 2, PREC>(p, s) : launch_stage_t<Sys5, 1, 1, PREC>(p, s);
   }
-  if (dim == 1) return order == 2 ? launch_stage_t<Sys14, 1, 2>(p, s) : launch_stage_t<Sys14, 1, 1>(p, s);
-  return order == 2 ? launch_stage_t<Sys14, 2, 2>(p, s) : launch_stage_t<Sys14, 2, 1>(p, s);
+  if (dim == 1)
+    return order == 2 ? launch_stage_t<Sys14, 1, 2, PREC>(p, s) : launch_stage_t<Sys14, 1, 1, PREC>(p, s);
+  return order == 2 ? launch_stage_t<Sys14, 2, 2, PREC>(p, s) : launch_stage_t<Sys14, 2, 1, PREC>(p, s);
+}
+
+hipError_t launch_stage(int system, int dim, int order, int precision, const StageParams& p,
+                        hipStream_t s) {
+  return precision == 0 ? launch_stage_p<0>(system, dim, order, p, s)
+                        : launch_stage_p<1>(system, dim, order, p, s);
 }
 
 hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s) {

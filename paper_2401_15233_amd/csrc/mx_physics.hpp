@@ -50,6 +50,16 @@ template <class T> MX_HD T tabs(T a) { return a < T(0) ? -a : a; }
 MX_HD double msqrt(double a) { return sqrt(a); }
 MX_HD double mexp(double a) { return exp(a); }
 MX_HD double mlog(double a) { return log(a); }
+// single precision: the hardware square root / exponential / logarithm (about 1 ulp)
+#if defined(__HIP_DEVICE_COMPILE__)
+MX_HD float msqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+MX_HD float mexp(float a) { return __expf(a); }
+MX_HD float mlog(float a) { return __logf(a); }
+#else
+MX_HD float msqrt(float a) { return sqrtf(a); }
+MX_HD float mexp(float a) { return expf(a); }
+MX_HD float mlog(float a) { return logf(a); }
+#endif
 
 // symmetric 3x3 (6 stored) times vector
 template <class T> MX_HD void symv(const T* S, const T* x, T* y) {
@@ -194,7 +204,7 @@ struct Sys14 {
 
   // Dimensionless state, sigma and P^-1 q.
   template <class T> struct Core {
-    T rho, c, Ph[6], qh[3], z[3], P2[6], t1, t2, sig, sb;
+    T rho, c, Ph[6], qh[3], z[3], P2[6], t1, t2, A, sig, sb;
   };
 
   template <class T> MX_HD static void core(const T* W, T sigma_lim, Core<T>& k) {
@@ -223,7 +233,47 @@ struct Sys14 {
     T D = k.qh[0] * k.z[0] + k.qh[1] * k.z[1] + k.qh[2] * k.z[2];
     T A = T(2) * k.t2 + k.t1 * k.t1 - Rh;
     T X = A * A + T(8) * k.t2 * D;
+    k.A = A;
     k.sig = sigma_root(A, X, T(2) * D, T(4) * k.t2);
+    k.sb = tmax(k.sig, sigma_lim);
+  }
+
+  // Mixed precision core: the bracket A = 2 tr(P*^2) + tr(P*)^2 - R* of the sigma mapping
+  // cancels near equilibrium (R* ~ 15 against A ~ 0), and the wave speeds scale like
+  // 1/sigma, so A and the traces it needs are formed in FP64; the rest in FP32.
+  MX_HD static void core_mixed(const double* W, float sigma_lim, Core<float>& k) {
+    double p = (W[4] + W[7] + W[9]) * (1.0 / 3.0);
+    double ip = 1.0 / p;
+    double Ph[6], P2[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) Ph[m] = W[4 + m] * ip;
+    symsq(Ph, P2);
+    double t1 = Ph[0] + Ph[3] + Ph[5];
+    double t2 = P2[0] + P2[3] + P2[5];
+    double A = 2.0 * t2 + t1 * t1 - W[13] * W[0] * ip * ip;
+    k.rho = (float)W[0];
+    float irho = 1.0f / k.rho;
+    float ipf = (float)ip;
+    k.c = msqrt((float)p * irho);
+    float ic = msqrt(k.rho * ipf);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { k.Ph[m] = (float)Ph[m]; k.P2[m] = (float)P2[m]; }
+    k.t1 = (float)t1;
+    k.t2 = (float)t2;
+    k.A = (float)A;
+    float is3 = irho * (ic * ic * ic);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k.qh[i] = (float)W[10 + i] * is3;
+    float C[6];
+    float det = symadj(k.Ph, C);
+    float idet = 1.0f / det;
+    float y[3];
+    symv(C, k.qh, y);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k.z[i] = y[i] * idet;
+    float D = k.qh[0] * k.z[0] + k.qh[1] * k.z[1] + k.qh[2] * k.z[2];
+    float X = k.A * k.A + 8.0f * k.t2 * D;
+    k.sig = sigma_root(k.A, X, 2.0f * D, 4.0f * k.t2);
     k.sb = tmax(k.sig, sigma_lim);
   }
 
@@ -354,6 +404,15 @@ struct Sys14 {
     wavespeeds<d>(k, W[1 + d], kws, lmin, lmax);
   }
 
+  // F_d and the wave speeds from a prepared core (mixed precision path)
+  template <int d, class T>
+  MX_HD static void flux_speeds(const Core<T>& k, const T* W, T kws, T* F, T& lmin, T& lmax) {
+    T Qd[6], Rd[3], Sd;
+    closure_dir<d>(k, Qd, Rd, Sd);
+    flux<d>(W, Qd, Rd, Sd, F);
+    wavespeeds<d>(k, W[1 + d], kws, lmin, lmax);
+  }
+
   // max(|lambda_min|, |lambda_max|) along d at a cell state
   template <int d, class T> MX_HD static T cell_lambda(const T* W, T sigma_lim, T kws) {
     Core<T> k;
@@ -427,7 +486,7 @@ struct Sys5 {
 
   MX_HD static constexpr bool odd(int v, int) { return v == 1 || v == 3; }
 
-  template <class T> struct Core { T rho, c, qh, sig, sb; };
+  template <class T> struct Core { T rho, c, qh, A, sig, sb; };
 
   template <class T> MX_HD static void core(const T* W, T sigma_lim, Core<T>& k) {
     k.rho = W[0];
@@ -440,7 +499,24 @@ struct Sys5 {
     T rh = W[4] * (is3 * ic);
     T A = T(3) - rh;
     T X = A * A + T(8) * k.qh * k.qh;
+    k.A = A;
     k.sig = sigma_root(A, X, T(2) * k.qh * k.qh, T(4));
+    k.sb = tmax(k.sig, sigma_lim);
+  }
+
+  MX_HD static void core_mixed(const double* W, float sigma_lim, Core<float>& k) {
+    double ip = 1.0 / W[2];
+    double A = 3.0 - W[4] * W[0] * ip * ip;
+    k.rho = (float)W[0];
+    float irho = 1.0f / k.rho;
+    float ipf = (float)ip;
+    k.c = msqrt((float)W[2] * irho);
+    float ic = msqrt(k.rho * ipf);
+    float is3 = irho * (ic * ic * ic);
+    k.qh = (float)W[3] * is3;
+    k.A = (float)A;
+    float X = k.A * k.A + 8.0f * k.qh * k.qh;
+    k.sig = sigma_root(k.A, X, 2.0f * k.qh * k.qh, 4.0f);
     k.sb = tmax(k.sig, sigma_lim);
   }
 
@@ -477,6 +553,12 @@ struct Sys5 {
     core(W, sigma_lim, k);
     flux(W, closing_s(k), F);
     prim_to_cons(W, U);
+    wavespeeds(k, W[1], kws, lmin, lmax);
+  }
+
+  template <int d, class T>
+  MX_HD static void flux_speeds(const Core<T>& k, const T* W, T kws, T* F, T& lmin, T& lmax) {
+    flux(W, closing_s(k), F);
     wavespeeds(k, W[1], kws, lmin, lmax);
   }
 

@@ -76,4 +76,74 @@ MX_HD void face_flux(const T* WL, const T* WR, T sigma_lim, T kws, int flux_kind
   }
 }
 
+// Mixed precision (Section 3.3: the dimensionless closure is robust in single precision).
+// The face states arrive in FP64 (primitive recovery and reconstruction stay FP64).  The
+// bracket A of the sigma mapping is formed in FP64 (it cancels near equilibrium); the rest of
+// the closure, the wave speeds and the physical flux of each face state are in FP32,
+// except near the Junk subspace (A < -MIX_DA and sigma < MIX_SIG_JUNK, where q^3/sigma^2 is
+// large) and near the realizability boundary (sigma > 1 - MIX_D1, where 1 - sigma and
+// sqrt(3 - 3 sigma) cancel): there the state is re-evaluated in FP64.  The HLL dissipation
+// term S_L S_R (U_R - U_L) / (S_R - S_L) uses FP64 conserved states, so that the jump is not
+// cancelled in FP32.  Returns the number of FP64 re-evaluations (0, 1 or 2).
+constexpr float MIX_DA = 1e-3f;
+constexpr float MIX_SIG_JUNK = 1e-2f;
+constexpr float MIX_D1 = 1e-3f;
+
+template <class SYS, int D>
+MX_HD void face_side_mixed(const double* W64, double sigma_lim, double kws, float* F, float& lmin,
+                           float& lmax, int& n64) {
+  constexpr int NV = SYS::NV;
+  float W[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) W[v] = (float)W64[v];
+  typename SYS::template Core<float> k;
+  SYS::core_mixed(W64, (float)sigma_lim, k);
+  bool near_junk = (k.A < -MIX_DA) && (k.sig < MIX_SIG_JUNK);
+  bool near_boundary = k.sig > 1.0f - MIX_D1;
+  if (near_junk || near_boundary || !(k.sig == k.sig)) {
+    double U[NV], F64[NV], a, b;
+    SYS::template face_terms<D>(W64, sigma_lim, kws, U, F64, a, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = (float)F64[v];
+    lmin = (float)a;
+    lmax = (float)b;
+    ++n64;
+  } else {
+    SYS::template flux_speeds<D>(k, W, (float)kws, F, lmin, lmax);
+  }
+}
+
+template <class SYS, int D>
+MX_HD void face_flux_mixed(const double* WL, const double* WR, double sigma_lim, double kws,
+                           int flux_kind, double* Fh, int& n64) {
+  constexpr int NV = SYS::NV;
+  float FL[NV], FR[NV], lminL, lmaxL, lminR, lmaxR;
+  face_side_mixed<SYS, D>(WL, sigma_lim, kws, FL, lminL, lmaxL, n64);
+  face_side_mixed<SYS, D>(WR, sigma_lim, kws, FR, lminR, lmaxR, n64);
+  double UL[NV], UR[NV];
+  SYS::prim_to_cons(WL, UL);
+  SYS::prim_to_cons(WR, UR);
+  if (flux_kind == 0) {
+    float SL = tmin(lminL, lminR), SR = tmax(lmaxL, lmaxR);
+    if (SL >= 0.0f) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fh[v] = (double)FL[v];
+    } else if (SR <= 0.0f) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fh[v] = (double)FR[v];
+    } else {
+      float inv = 1.0f / (SR - SL);
+      double diss = (double)SL * (double)SR / ((double)SR - (double)SL);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        Fh[v] = (double)((SR * FL[v] - SL * FR[v]) * inv) + diss * (UR[v] - UL[v]);
+    }
+  } else {
+    float am = tmax(tmax(tabs(lminL), tabs(lmaxL)), tmax(tabs(lminR), tabs(lmaxR)));
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      Fh[v] = (double)(0.5f * (FL[v] + FR[v])) - 0.5 * (double)am * (UR[v] - UL[v]);
+  }
+}
+
 }  // namespace mx

@@ -278,3 +278,13 @@ def batch_instances(n_inst=512, seed=20240127, n_lo=512, n_hi=32768):
 def kn_to_tau_ref(kn, L_ref=1.0, T_ref=1.0):
     """tau_ref = lambda / v_th with lambda = Kn L_ref and v_th = sqrt(8 T_ref / pi)."""
     return kn * L_ref / math.sqrt(8.0 * T_ref / math.pi)
+
+
+def batch_sod_prims(instances):
+    """Concatenated primitive field of batched shock tubes: instance i has left (rho, p) =
+    (1, 1) and right (1/rho_ratio, 1/p_ratio), at rest, Maxwellian, diaphragm at 0.5 of [0, 1]."""
+    parts = []
+    for d in instances:
+        right = (1.0 / d['rho_ratio'], 0.0, 1.0 / d['p_ratio'])
+        parts.append(sod_prims(14, d['n'], left=(1.0, 0.0, 1.0), right=right))
+    return np.concatenate(parts, axis=1)

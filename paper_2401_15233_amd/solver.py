@@ -21,11 +21,13 @@ FLUX = {'hll': 0, 'rusanov': 1}
 INTEGRATOR = {'fe': 0, 'ssprk2': 1, 'midpoint': 2}
 TAU_MODE = {'local': 0, 'const': 1}
 REPR = {'primitive': 0, 'conserved': 1, 'sigma': 2}
-PRECISION = {'fp64': 0}
+PRECISION = {'fp64': 0, 'mixed': 2}
 
 EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_moments',
             'maxent_num_vars', 'maxent_get_info', 'maxent_destroy', 'maxent_last_error',
-            'maxent_abi_version', 'maxent_set_profiling', 'maxent_get_profile')
+            'maxent_abi_version', 'maxent_set_profiling', 'maxent_get_profile',
+            'maxent_create_batch', 'maxent_step_batch', 'maxent_set_batch_launch',
+            'maxent_get_batch_launch', 'maxent_autotune_batch')
 
 
 class MaxentError(RuntimeError):
@@ -56,6 +58,27 @@ class Numerics(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [('t', ctypes.c_double), ('dt_last', ctypes.c_double),
                 ('steps', ctypes.c_longlong), ('n_fallback', ctypes.c_longlong),
+                ('fail_step', ctypes.c_int), ('fail_code', ctypes.c_int),
+                ('n_fp64_states', ctypes.c_longlong), ('n_face_states', ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [('x0', ctypes.c_double), ('x1', ctypes.c_double), ('tau_ref', ctypes.c_double),
+                ('t_end', ctypes.c_double), ('n_cells', ctypes.c_int), ('pad', ctypes.c_int)]
+
+
+class InstanceInfo(ctypes.Structure):
+    _fields_ = [('t', ctypes.c_double), ('dt_last', ctypes.c_double), ('steps', ctypes.c_longlong),
+                ('fail_step', ctypes.c_int), ('fail_code', ctypes.c_int)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [('max_steps', ctypes.c_longlong), ('cell_updates', ctypes.c_longlong),
+                ('n_active', ctypes.c_longlong), ('n_fallback', ctypes.c_longlong),
+                ('n_fp64_states', ctypes.c_longlong), ('n_face_states', ctypes.c_longlong),
                 ('fail_step', ctypes.c_int), ('fail_code', ctypes.c_int)]
 
     def as_dict(self):
@@ -88,6 +111,14 @@ def load_library(path=LIB_PATH):
     L.maxent_last_error.restype = ctypes.c_char_p
     L.maxent_abi_version.argtypes = []
     L.maxent_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.maxent_create_batch.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Numerics), ctypes.c_int,
+                                      ctypes.POINTER(Instance), vp, ctypes.POINTER(vp)]
+    L.maxent_step_batch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BatchInfo),
+                                    ctypes.POINTER(InstanceInfo)]
+    L.maxent_set_batch_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.maxent_get_batch_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.maxent_autotune_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.maxent_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong)]
     _lib = L
@@ -224,3 +255,72 @@ class MaxEntSolver:
             out = torch.empty(shape, dtype=torch.float64, device='cuda')
         self._check(self._lib.maxent_get_moments(self._h, REPR[repr], ctypes.c_void_p(out.data_ptr()), 1))
         return out
+
+
+class MaxEntBatch(MaxEntSolver):
+    """Many independent 1D 14-moment tubes advanced together (maxent_create_batch).
+
+    instances: list of dicts with n (cells), tau_ref, t_end and optionally x0, x1.  The field
+    of init_state / get is the concatenation [14][sum n]."""
+
+    def __init__(self, instances, stream=None, **kw):
+        self._lib = load_library()
+        torch = _torch()
+        pk = {k: v for k, v in kw.items() if k in _PROBLEM_KEYS}
+        nk = {k: v for k, v in kw.items() if k not in _PROBLEM_KEYS}
+        pk.setdefault('system', 14)
+        self.problem = make_problem(**pk)
+        self.numerics = make_numerics(**nk)
+        arr = (Instance * len(instances))()
+        for k, d in enumerate(instances):
+            arr[k].x0 = d.get('x0', 0.0)
+            arr[k].x1 = d.get('x1', 1.0)
+            arr[k].tau_ref = d.get('tau_ref', 0.0)
+            arr[k].t_end = d['t_end']
+            arr[k].n_cells = int(d['n'])
+        self.n_inst = len(instances)
+        self.sizes = [int(d['n']) for d in instances]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        rc = self._lib.maxent_create_batch(ctypes.byref(self.problem), ctypes.byref(self.numerics),
+                                           self.n_inst, arr, ctypes.c_void_p(stream.cuda_stream),
+                                           ctypes.byref(h))
+        if rc != MAXENT_OK:
+            raise MaxentError(rc, self._lib.maxent_last_error(None).decode())
+        self._h = h
+        self.nv = 14
+        self.shape = (14, 1, int(self.offsets[-1]))
+
+    def step(self, max_steps=10 ** 9, chunk=100, check=True):
+        info = BatchInfo()
+        per = (InstanceInfo * self.n_inst)()
+        rc = self._lib.maxent_step_batch(self._h, int(max_steps), int(chunk), ctypes.byref(info), per)
+        if check:
+            self._check(rc)
+        d = info.as_dict()
+        d['status'] = STATUS.get(rc, 'OK') if rc else 'OK'
+        d['instances'] = [{k: getattr(per[i], k) for k, _ in InstanceInfo._fields_}
+                          for i in range(self.n_inst)]
+        return d
+
+    def set_launch(self, threads, wg_per_cu):
+        self._check(self._lib.maxent_set_batch_launch(self._h, int(threads), int(wg_per_cu)))
+
+    def launch(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.maxent_get_batch_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, trial_steps=20):
+        a, b, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(self._lib.maxent_autotune_batch(self._h, int(trial_steps), ctypes.byref(a),
+                                                    ctypes.byref(b), ctypes.byref(r)))
+        return {'threads': a.value, 'wg_per_cu': b.value, 'cell_updates_per_s': r.value}
+
+    def split(self, field):
+        """Per-instance views [14][n_i] of a concatenated field."""
+        f = field.reshape(field.shape[0], -1)
+        return [f[:, self.offsets[i]:self.offsets[i + 1]] for i in range(self.n_inst)]

@@ -152,7 +152,7 @@ def oracle_cells_1d(W, cells, kw, nsteps, dt, tau_ref, trials=3, seed=0):
     return np.array(vals).T, np.array(spreads).T
 
 
-def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0):
+def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0, perturb=PERTURB, nsteps=None):
     """Long runs: the oracle's result at t_end, its L1 spread per moment (largest
     ||perturbed - base||_1 over +-4 ulp input perturbations) and the largest change of the
     step count under the same perturbations."""
@@ -160,13 +160,14 @@ def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0):
     U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
     if s.dim == 1:
         U0 = U0.reshape(U0.shape[0], -1)
-    base, t, n = sc.run(U0, s, tau_ref, t_end=t_end)
+    kwr = dict(t_end=t_end if t_end and t_end > 0 else None, nsteps=nsteps)
+    base, t, n = sc.run(U0, s, tau_ref, **kwr)
     rng = np.random.default_rng(seed)
     spread = np.zeros(base.shape[0])
     nspread = 0
     for _ in range(trials):
-        Up = U0 * (1.0 + rng.choice([-1.0, 1.0], U0.shape) * PERTURB)
-        out, _, nk = sc.run(Up, s, tau_ref, t_end=t_end)
+        Up = U0 * (1.0 + rng.choice([-1.0, 1.0], U0.shape) * perturb)
+        out, _, nk = sc.run(Up, s, tau_ref, **kwr)
         spread = np.maximum(spread, np.abs(out - base).reshape(base.shape[0], -1).sum(1))
         nspread = max(nspread, abs(nk - n))
     return base, spread, t, n, nspread

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(S.Problem) == 4 * 4 + 4 * 8 + 4 * 4 + 4 + 4 + 12 * 8 + 3 * 8 + 8 + 2 * 8
     assert S.Problem.x0.offset == 16 and S.Problem.n_jets.offset == 64
     assert ctypes.sizeof(S.Numerics) == 5 * 4 + 4 + 3 * 8 + 8
-    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
 
 
 @pytest.mark.parametrize('bad', [
@@ -78,3 +78,20 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.maxent_get_moments(None, 0, None, 0) == -1
     assert lib.maxent_num_vars(None) == 0
     lib.maxent_destroy(None)
+
+
+@pytest.mark.parametrize('bad', [dict(system=5), dict(order=1), dict(integrator='fe'),
+                                 dict(n=3), dict(x1=-1.0), dict(t_end=0.0)])
+def test_create_batch_rejects_bad_arguments(lib, bad):
+    prob_kw = {'system': bad.get('system', 14)}
+    num_kw = {k: v for k, v in bad.items() if k in ('order', 'integrator')}
+    p = S.make_problem(**prob_kw)
+    n = S.make_numerics(**num_kw)
+    inst = (S.Instance * 2)()
+    for k in range(2):
+        inst[k].x0, inst[k].x1 = 0.0, bad.get('x1', 1.0)
+        inst[k].tau_ref, inst[k].t_end = 0.01, bad.get('t_end', 0.1)
+        inst[k].n_cells = bad.get('n', 64)
+    h = ctypes.c_void_p()
+    assert lib.maxent_create_batch(ctypes.byref(p), ctypes.byref(n), 2, inst, None, ctypes.byref(h)) == -1
+    assert not h.value

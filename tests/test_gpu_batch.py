@@ -1,0 +1,107 @@
+"""Batched 1D tubes (maxent_create_batch / maxent_step_batch) through the C-ABI.
+
+The batched kernel runs the single-instance 1D kernel's per-cell arithmetic (same device
+functions, same update), so each batched instance must equal the same instance run alone
+bit for bit, whatever launch shape the autotuner picks; the single-instance path is itself
+checked against the oracle (test_gpu_parity.py), and a few small instances are checked
+against the oracle directly here."""
+import numpy as np
+import pytest
+
+from paper_2401_15233_amd import inputs as I
+import oracle_bridge as ob
+
+pytestmark = pytest.mark.gpu
+
+NUM = dict(order=2, integrator='ssprk2', flux='hll', limiter='minmod', cfl=0.5)
+
+
+def small_batch(seed=5, n=7):
+    rng = np.random.default_rng(seed)
+    sizes = [100, 63, 64, 257, 500, 33, 1000][:n]
+    out = []
+    for k in range(n):
+        out.append(dict(n=sizes[k], p_ratio=float(rng.uniform(2, 100)), rho_ratio=float(rng.uniform(2, 20)),
+                        kn=float(np.exp(rng.uniform(np.log(1e-3), np.log(10)))), t_end=0.01 + 0.01 * k))
+    for d in out:
+        d['tau_ref'] = I.kn_to_tau_ref(d['kn'])
+    return out
+
+
+def run_batch(S, insts, precision='fp64', launch=None, autotune=False):
+    b = S.MaxEntBatch(insts, precision=precision, **NUM)
+    b.init_state(I.batch_sod_prims(insts))
+    tuned = None
+    if autotune:
+        tuned = b.autotune(trial_steps=3)
+    if launch:
+        b.set_launch(*launch)
+    info = b.step(chunk=16)
+    U = b.get('conserved').cpu().numpy()
+    parts = [p.copy() for p in b.split(U)]
+    b.close()
+    return parts, info, tuned
+
+
+def run_single(S, d, precision='fp64'):
+    s = S.MaxEntSolver(system=14, dim=1, nx=d['n'], precision=precision, **NUM)
+    s.init_state(I.batch_sod_prims([d]))
+    info = s.step(10 ** 6, tau_ref=d['tau_ref'], t_end=d['t_end'])
+    U = s.get('conserved').cpu().numpy()[:, 0, :]
+    s.close()
+    return U, info
+
+
+@pytest.mark.parametrize('precision', ['fp64', 'mixed'])
+def test_batch_equals_instances_run_alone_bitwise(gpu_lib, precision):
+    insts = small_batch()
+    parts, info, _ = run_batch(gpu_lib, insts, precision)
+    assert info['n_active'] == 0
+    for d, Ub, pi in zip(insts, parts, info['instances']):
+        Us, si = run_single(gpu_lib, d, precision)
+        assert pi['steps'] == si['steps'] and pi['t'] == si['t']
+        assert np.array_equal(Ub, Us), d
+
+
+@pytest.mark.parametrize('launch', [(64, 2), (128, 4), (256, 8), (64, 16)])
+def test_batch_launch_shapes_do_not_change_results(gpu_lib, launch):
+    insts = small_batch(seed=8)
+    ref, _, _ = run_batch(gpu_lib, insts, launch=(64, 4))
+    got, _, _ = run_batch(gpu_lib, insts, launch=launch)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_batch_autotune_keeps_state_and_results(gpu_lib):
+    insts = small_batch(seed=9)
+    ref, _, _ = run_batch(gpu_lib, insts, launch=(64, 4))
+    got, info, tuned = run_batch(gpu_lib, insts, autotune=True)
+    print('autotuned launch', tuned, flush=True)
+    assert tuned['threads'] in (64, 128, 256) and tuned['cell_updates_per_s'] > 0
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_batch_small_instances_against_oracle(gpu_lib):
+    insts = [dict(n=80, p_ratio=10.0, rho_ratio=8.0, kn=0.01, t_end=0.02),
+             dict(n=131, p_ratio=50.0, rho_ratio=3.0, kn=1.0, t_end=0.015),
+             dict(n=64, p_ratio=2.5, rho_ratio=15.0, kn=1e-3, t_end=0.03)]
+    for d in insts:
+        d['tau_ref'] = I.kn_to_tau_ref(d['kn'])
+    parts, info, _ = run_batch(gpu_lib, insts)
+    for d, Ub in zip(insts, parts):
+        kw = dict(system=14, dim=1, nx=d['n'], **NUM)
+        base, spread, t, n, nspread = ob.oracle_with_l1_spread(kw, I.batch_sod_prims([d]), d['t_end'],
+                                                               d['tau_ref'])
+        d1 = np.abs(Ub - base).sum(1)
+        b1 = np.maximum(np.abs(base).sum(1), 1e-300)
+        print(f"instance n={d['n']}: L1 relative error {np.array2string(d1 / b1, precision=1)}", flush=True)
+        assert np.all(d1 <= 1e-12 * b1 + ob.SPREAD_FACTOR * spread)
+
+
+def test_batch_collisionless_instance_and_status(gpu_lib):
+    insts = small_batch(seed=3, n=3)
+    insts[1]['tau_ref'] = 0.0
+    parts, info, _ = run_batch(gpu_lib, insts)
+    assert info['status'] == 'OK' and info['fail_code'] == 0
+    assert all(abs(p['t'] - d['t_end']) < 1e-14 for p, d in zip(info['instances'], insts))
