@@ -212,6 +212,56 @@ int maxent_get_batch_launch(maxent_solver* s, int* threads, int* wg_per_cu);
 int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* wg_per_cu,
                           double* best_cell_updates_per_s);
 
+/* ------------------------------------------------------------------ discrete adjoint
+ * Reverse-mode derivatives of a scalar J(U_final) through the recorded steps: the hand-written
+ * adjoint of every piece of the step (the conserved map and primitive recovery, the limited
+ * reconstruction of Section 3.2, the closure of Section 2.4 / Appendix A with its sigma
+ * mapping and sigma limit, the wave speeds of Section 5.1, the HLL / Rusanov flux of
+ * Section 3.1, the BGK source with its local relaxation time, the boundary conditions and the
+ * Runge-Kutta stages).  Conventions:
+ *   - 14-moment system, FP64 precision, not a batch solver.
+ *   - The time steps are frozen: the reverse replays the dt sequence the forward run used and
+ *     does not differentiate the CFL maximum.
+ *   - At non-smooth points the branch the forward evaluation took is differentiated: the
+ *     limiter's selected variable and regime (a factor of 0 or 1 is constant), the
+ *     positivity fallback, max(sigma, sigma_lim) (no derivative through sigma when the limit
+ *     is active), min(sigma, 1) in the wave speeds, the clamped square roots, the HLL case.
+ *   - Parameters: the jet Mach number and jet density of the JET boundary, and tau_ref (the
+ *     derivative with respect to one tau_ref shared by all recorded steps, each step's source
+ *     scaling as 1/tau_ref). */
+
+/* Start recording a tape at the current state (checkpoint_every >= 1), or stop and free it
+ * (checkpoint_every = 0).  While recording, maxent_step keeps each step's time step on the
+ * device and its tau_ref on the host, and a copy of the state every checkpoint_every steps;
+ * at most max_steps steps can be recorded (a maxent_step call that would exceed it fails with
+ * INVAL before doing anything).  Device memory: (max_steps / checkpoint_every + 1) states for
+ * the checkpoints; the adjoint adds 2 checkpoint_every + 3 states plus face and cell
+ * workspaces (about 6 states in 2D).  maxent_init_state and maxent_destroy end the tape.
+ * Errors: INVAL (sizes), STATE (no valid state, batch solver), NOMEM. */
+int maxent_record(maxent_solver* s, int checkpoint_every, int max_steps);
+
+/* Jet inflow Mach number and density of the JET boundary (both > 0).  Not allowed while a
+ * tape holds recorded steps (STATE). */
+int maxent_set_inflow(maxent_solver* s, double mach, double rho);
+
+/* Steps recorded on the tape, and (dt != NULL) their time steps: dt must hold n_steps
+ * doubles (host).  Replaying them as fixed time steps reproduces the recorded run bit for
+ * bit.  Errors: STATE (no tape), DEVICE. */
+int maxent_tape_info(maxent_solver* s, long long* n_steps, double* dt);
+
+/* Reverse all recorded steps.
+ *   dJ_dU       dJ/dU at the final state: conserved field array (14 x ny x nx), host or device.
+ *   dJ_dU0      optional output (NULL: skipped): dJ/dU at the tape's start, same layout.
+ *   dJ_dparams  optional host output of 3 doubles: dJ/d(jet Mach), dJ/d(jet rho), dJ/d tau_ref
+ *               (0 for a parameter that does not enter, e.g. no JET boundary, tau_ref <= 0).
+ * Segment by segment, newest first, the steps between two checkpoints are recomputed from the
+ * checkpoint with the recorded time steps (bitwise the forward states) and reversed stage by
+ * stage.  The solver's state, time and counters are not changed; the tape stays valid, so the
+ * call may be repeated for another dJ_dU.  Errors: INVAL (null dJ_dU), STATE (no tape, or
+ * the recorded run failed), NOMEM, DEVICE. */
+int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ_on_device, double* dJ_dU0,
+                        int dU0_on_device, double* dJ_dparams);
+
 /* Optional timing of the fused stage kernels: when enabled, every stage-kernel launch of
  * maxent_step is bracketed by HIP events on the solver's stream and the elapsed times are
  * accumulated (read at the end of each maxent_step call).  Enabling resets the totals. */

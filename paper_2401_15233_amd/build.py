@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libmaxent.so')
-SOURCES = ['mx_api.hip', 'mx_kernels.hip', 'mx_batch.hip']
+SOURCES = ['mx_api.hip', 'mx_kernels.hip', 'mx_batch.hip', 'mx_adjoint.hip']
 ARCH = os.environ.get('MAXENT_OFFLOAD_ARCH', 'gfx950')
 
 

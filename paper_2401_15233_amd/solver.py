@@ -27,7 +27,8 @@ EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_mom
             'maxent_num_vars', 'maxent_get_info', 'maxent_destroy', 'maxent_last_error',
             'maxent_abi_version', 'maxent_set_profiling', 'maxent_get_profile',
             'maxent_create_batch', 'maxent_step_batch', 'maxent_set_batch_launch',
-            'maxent_get_batch_launch', 'maxent_autotune_batch')
+            'maxent_get_batch_launch', 'maxent_autotune_batch', 'maxent_record',
+            'maxent_set_inflow', 'maxent_step_adjoint', 'maxent_tape_info')
 
 
 class MaxentError(RuntimeError):
@@ -121,6 +122,11 @@ def load_library(path=LIB_PATH):
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.maxent_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong)]
+    L.maxent_record.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.maxent_set_inflow.argtypes = [vp, ctypes.c_double, ctypes.c_double]
+    L.maxent_tape_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), vp]
+    L.maxent_step_adjoint.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
 
@@ -255,6 +261,44 @@ class MaxEntSolver:
             out = torch.empty(shape, dtype=torch.float64, device='cuda')
         self._check(self._lib.maxent_get_moments(self._h, REPR[repr], ctypes.c_void_p(out.data_ptr()), 1))
         return out
+
+
+    # ---------------------------------------------------------------- discrete adjoint
+    def record(self, checkpoint_every, max_steps):
+        """Start a tape at the current state (checkpoint_every = 0 ends it)."""
+        self._check(self._lib.maxent_record(self._h, int(checkpoint_every), int(max_steps)))
+
+    def set_inflow(self, mach, rho):
+        self._check(self._lib.maxent_set_inflow(self._h, float(mach), float(rho)))
+        self.problem.jet_mach, self.problem.jet_rho = float(mach), float(rho)
+
+    def tape(self):
+        """Time steps of the recorded steps (NumPy array)."""
+        n = ctypes.c_longlong()
+        self._check(self._lib.maxent_tape_info(self._h, ctypes.byref(n), None))
+        dt = np.zeros(max(n.value, 1))
+        self._check(self._lib.maxent_tape_info(self._h, ctypes.byref(n), dt.ctypes.data_as(ctypes.c_void_p)))
+        return dt[:n.value]
+
+    def adjoint(self, dJ_dU, want_dU0=True):
+        """Reverse the tape: returns (dJ/dU0 as a CUDA tensor or None, [dJ/dM, dJ/drho_jet,
+        dJ/dtau_ref]).  dJ_dU: conserved-shaped CUDA tensor or NumPy array."""
+        torch = _torch()
+        g = (ctypes.c_double * 3)()
+        out = torch.empty(self.shape, dtype=torch.float64, device='cuda') if want_dU0 else None
+        optr = ctypes.c_void_p(out.data_ptr()) if want_dU0 else None
+        if isinstance(dJ_dU, np.ndarray):
+            a = np.ascontiguousarray(dJ_dU, dtype=np.float64)
+            if a.size != int(np.prod(self.shape)):
+                raise ValueError(f'dJ_dU must have shape {self.shape}')
+            rc = self._lib.maxent_step_adjoint(self._h, a.ctypes.data_as(ctypes.c_void_p), 0, optr, 1, g)
+        else:
+            a = dJ_dU.to(dtype=torch.float64).contiguous()
+            if a.numel() != int(np.prod(self.shape)) or not a.is_cuda:
+                raise ValueError(f'dJ_dU must be a CUDA tensor with shape {self.shape}')
+            rc = self._lib.maxent_step_adjoint(self._h, ctypes.c_void_p(a.data_ptr()), 1, optr, 1, g)
+        self._check(rc)
+        return out, [g[0], g[1], g[2]]
 
 
 class MaxEntBatch(MaxEntSolver):

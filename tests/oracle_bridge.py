@@ -171,3 +171,28 @@ def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0, perturb=PERT
         spread = np.maximum(spread, np.abs(out - base).reshape(base.shape[0], -1).sum(1))
         nspread = max(nspread, abs(nk - n))
     return base, spread, t, n, nspread
+
+
+# ---------------------------------------------------------------- adjoint references
+def oracle_objective(kw, U0, weights, nsteps, dt, tau_ref, mach=None, rho=None):
+    """J = sum(weights * U_n) after nsteps oracle steps of fixed dt from the conserved U0
+    (a linear functional of the final state; dt frozen as in the discrete adjoint)."""
+    s = to_setup(kw)
+    if mach is not None:
+        s.jet_mach = mach
+    if rho is not None:
+        s.jet_rho = rho
+    U = np.array(U0, dtype=float)
+    if s.dim == 1:
+        U = U.reshape(U.shape[0], -1)
+    Un, _, n = sc.run(U, s, tau_ref, nsteps=nsteps, dt=dt)
+    assert n == nsteps
+    return float((np.asarray(weights).reshape(Un.shape) * Un).sum())
+
+
+def central_difference(f, x, h):
+    """(f(x + h) - f(x - h)) / 2h at step h and at 2h; the difference of the two estimates
+    the truncation error of the first (3x its size, with smooth f)."""
+    d1 = (f(x + h) - f(x - h)) / (2 * h)
+    d2 = (f(x + 2 * h) - f(x - 2 * h)) / (4 * h)
+    return d1, d2
