@@ -96,6 +96,56 @@ def cpu_baseline(n=128, steps=5):
                       f'{wall:.1f} s wall'}
 
 
+def adjoint_record(stream, n=512, steps=400, checkpoint_every=20):
+    """Discrete adjoint of the crossed jets (14 moments, FP64): n x n cells from the background
+    state, `steps` CFL steps recorded with a checkpoint every `checkpoint_every`, reversed for
+    J = dx dy sum of rho u_y over x in [0.05, 0.15], y in [0.5, 1] (a strip the jets reach in
+    400 steps).  Times the plain forward run, the recording forward run and the adjoint
+    (recomputation of every checkpoint segment included) with HIP events on the solver's
+    stream."""
+    import numpy as np
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+    tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
+    W0 = inputs.crossed_jets_initial(n, n)
+    s = solver.MaxEntSolver(stream=stream, **jets_kwargs(n))
+    w = np.zeros((14, n, n))
+    xc = (np.arange(n) + 0.5) / n
+    box = ((xc[None, :] >= 0.05) & (xc[None, :] <= 0.15) & (xc[:, None] >= 0.5))
+    w[2][box] = 1.0 / (n * n)
+    wt = torch.tensor(w, device='cuda')
+
+    def clock(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), r
+
+    s.init_state(W0)
+    s.step(3, tau_ref=tau)                       # warm-up
+    s.init_state(W0)
+    fwd_ms, _ = clock(lambda: s.step(steps, tau_ref=tau))
+    s.init_state(W0)
+    s.record(checkpoint_every, steps)
+    rec_ms, info = clock(lambda: s.step(steps, tau_ref=tau))
+    Un = s.get('conserved')
+    s.adjoint(wt, want_dU0=False)                # workspace allocation outside the timing
+    adj_ms, (gU0, g) = clock(lambda: s.adjoint(wt, want_dU0=True))
+    J = float((wt * Un).sum())
+    s.close()
+    return {'workload': f'2D crossed jets, 14-moment FP64, {n}x{n}, {steps} CFL steps '
+                        f'(t = {info["t"]:.4f}), checkpoint every {checkpoint_every}',
+            'objective': 'dx dy sum of rho u_y over x in [0.05, 0.15], y in [0.5, 1]',
+            'J': J, 'dJ_dMach': g[0], 'dJ_drho_jet': g[1], 'dJ_dtau_ref': g[2],
+            'forward_ms': fwd_ms, 'forward_recording_ms': rec_ms, 'adjoint_ms': adj_ms,
+            'adjoint_over_forward': adj_ms / fwd_ms,
+            'forward_cell_updates_per_s': n * n * steps / (fwd_ms / 1e3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -106,6 +156,8 @@ def main():
     ap.add_argument('--precision', default='both', choices=('fp64', 'mixed', 'both'),
                     help='fp64 (the headline value), mixed, or both (fp64 headline plus a mixed '
                          'sub-record with its L1 deviation from the FP64 run)')
+    ap.add_argument('--no-adjoint', action='store_true',
+                    help='skip the adjoint / forward timing of the 512^2 crossed jets')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a plain 2 GiB device copy (HBM counter calibration)')
     a = ap.parse_args()
@@ -206,6 +258,8 @@ def main():
             'fp64_reevaluated_face_state_fraction':
                 info_m['n_fp64_states'] / max(info_m['n_face_states'], 1),
         }
+    if not a.no_adjoint:
+        out['adjoint'] = adjoint_record(stream)
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()
     print(json.dumps(out), flush=True)

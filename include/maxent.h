@@ -249,6 +249,18 @@ int maxent_set_inflow(maxent_solver* s, double mach, double rho);
  * bit.  Errors: STATE (no tape), DEVICE. */
 int maxent_tape_info(maxent_solver* s, long long* n_steps, double* dt);
 
+/* What the reverse pass differentiates (default EXACT).
+ *   MAXENT_ADJ_EXACT           the exact derivative of the discrete step (branch replayed).
+ *   MAXENT_ADJ_FROZEN_LIMITER  the same with each cell's common limiter factor held at its
+ *                              forward value (no derivative through the limiter's selection).
+ * Over long horizons the exact derivative of the common-limiter scheme grows without bound:
+ * one variable's jumps set the factor applied to all fourteen slopes, and these cross-variable
+ * gains compound from stage to stage, so J becomes rough on scales far below any practical
+ * perturbation (the exact derivative, while correct, no longer predicts finite differences).
+ * The frozen-limiter derivative stays bounded.  Errors: INVAL (unknown mode). */
+enum { MAXENT_ADJ_EXACT = 0, MAXENT_ADJ_FROZEN_LIMITER = 1 };
+int maxent_set_adjoint_mode(maxent_solver* s, int mode);
+
 /* Reverse all recorded steps.
  *   dJ_dU       dJ/dU at the final state: conserved field array (14 x ny x nx), host or device.
  *   dJ_dU0      optional output (NULL: skipped): dJ/dU at the tape's start, same layout.

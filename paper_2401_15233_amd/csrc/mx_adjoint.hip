@@ -4,12 +4,17 @@
 //   L_c = -(F_{c+1/2} - F_{c-1/2}) / dx - (G_{c+1/2} - G_{c-1/2}) / dy + C(W_c)
 // (Section 3: HLL / Rusanov interface fluxes of MUSCL face states built with the common
 // limiter, BGK source at the cell centre, ghost cells from the boundary conditions).
-// Its reverse runs in three deterministic gather passes plus a reduction:
-//   1. faces (adj_face_kernel, per direction): rebuild the two face states of every face from
-//      the stage input, take the flux adjoint Fb = (mu_right - mu_left) / dx from the two
-//      adjacent cells (mu = mu_coef dt lam_out, zero in ghost cells) and reverse the interface
-//      flux, closure, wave speeds and conserved map of both face states (branch replayed);
-//      store the two face-state adjoints;
+// Its reverse runs as deterministic gather passes plus a reduction:
+//   0. prep (adj_prim_kernel, adj_limiter_kernel): primitives of every cell of the domain
+//      and its two ghost layers, and each cell's common limiter factor and the variable that
+//      selected it, per direction (the forward stage's values, bit for bit);
+//   1. faces, per direction: (a) adj_face_a_kernel rebuilds the two face states of every
+//      face, evaluates their closure, wave speeds, fluxes and conserved states, takes the
+//      flux adjoint Fb = (mu_right - mu_left) / dx from the two adjacent cells
+//      (mu = mu_coef dt lam_out, zero in ghost cells) and reverses the HLL / Rusanov
+//      combination (branch replayed), writing a record per face side; (b) adj_face_b_kernel
+//      reverses closure, wave speeds, physical flux and conserved map of one face side per
+//      thread (split from (a) to keep each thread's live state in registers);
 //   2. extended cells (adj_cell_kernel): for every cell of the domain and its two ghost
 //      layers, gather the reverse of the limited reconstruction of the up to three stencil
 //      cells whose face states it feeds (limiter argmin, regime and fallback replayed);
@@ -19,7 +24,8 @@
 //      primitive adjoint back to conserved variables and combine with beta lam_out and the
 //      later stage's contribution;
 //   4. adj_reduce_kernel: sum the per-workgroup parameter partials in a fixed order.
-// No atomics: the result is bitwise reproducible.
+// No atomics: the result is bitwise reproducible.  Faces whose flux adjoint is exactly zero
+// (outside the adjoint's domain of dependence) skip the closure reverse.
 #include "mx_internal.hpp"
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
@@ -34,31 +40,68 @@ __device__ __forceinline__ long long ucell(const StageParams& p, int i, int j) {
   return (long long)j * p.pitch + i;
 }
 
-// common limiter factor of the cell with stencil (Wm, Wc, Wp), as the forward stage computes it
-__device__ __forceinline__ double forward_phi(const StageParams& p, const double* Wm, const double* Wc,
-                                              const double* Wp) {
-  double phi = limiter_factor<Sys14>(Wm, Wc, Wp, p.limiter);
-  if (p.fallback && phi > 0.0) {
-    double Wf[14];
-    face_state<Sys14>(Wm, Wc, Wp, phi, 1.0, Wf);
-    bool ok = Sys14::admissible(Wf);
-    face_state<Sys14>(Wm, Wc, Wp, phi, -1.0, Wf);
-    ok = ok && Sys14::admissible(Wf);
-    if (!ok) phi = 0.0;
-  }
-  return phi;
+// extended-cell index of cell c of line l along direction D
+template <int D, int DIM>
+__device__ __forceinline__ long long ext_idx(const AdjParams& a, int c, int l) {
+  if (D == 0) return (long long)((DIM == 2) ? l + 2 : 0) * a.epitch + (c + 2);
+  return (long long)(c + 2) * a.epitch + (l + 2);
 }
 
-// load the primitive state of (possibly ghost) cell c along direction D of line l
-template <int D>
-__device__ __forceinline__ void line_prims(const StageParams& p, int c, int l, double* W) {
-  if (D == 0) load_prims<Sys14>(p, p.Ub, c, l, W);
-  else load_prims<Sys14>(p, p.Ub, l, c, W);
+__device__ __forceinline__ void get_w(const AdjParams& a, long long e, double* W) {
+#pragma unroll
+  for (int v = 0; v < 14; ++v) W[v] = a.wext[v * a.eplane + e];
+}
+
+// ------------------------------------------------------------------ 0. prep
+template <int DIM>
+__global__ __launch_bounds__(ADJ_NT) void adj_prim_kernel(AdjParams a) {
+  const long long e = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  if (e >= a.eplane) return;
+  const int i = (int)(e % a.epitch) - 2;
+  const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
+  double W[14];
+  load_prims<Sys14>(a.sp, a.sp.Ub, i, j, W);
+#pragma unroll
+  for (int v = 0; v < 14; ++v) a.wext[v * a.eplane + e] = W[v];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
+  const StageParams& p = a.sp;
+  const long long e = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  if (e >= a.eplane) return;
+  const int i = (int)(e % a.epitch) - 2;
+  const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
+  double Wm[14], Wc[14], Wp[14];
+  double phi = 0.0;
+  int vs = -1;
+  if (j >= 0 && j < p.ny && i >= -1 && i <= p.nx) {
+    get_w(a, e - 1, Wm);
+    get_w(a, e, Wc);
+    get_w(a, e + 1, Wp);
+    phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
+  }
+  a.phix[e] = phi;
+  a.vsx[e] = a.frozen_limiter ? -1 : vs;
+  if constexpr (DIM == 2) {
+    phi = 0.0;
+    vs = -1;
+    if (i >= 0 && i < p.nx && j >= -1 && j <= p.ny) {
+      get_w(a, e - a.epitch, Wm);
+      get_w(a, e, Wc);
+      get_w(a, e + a.epitch, Wp);
+      phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
+    }
+    a.phiy[e] = phi;
+    a.vsy[e] = a.frozen_limiter ? -1 : vs;
+  }
 }
 
 // ------------------------------------------------------------------ 1. faces
-template <int D, int ORDER>
-__global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
+// side record layout: [0,14) W, [14,28) U-bar, [28,42) F-bar, 42 lambda_min-bar,
+// 43 lambda_max-bar; record r of face fo: left side r = fo, right side r = nf + fo
+template <int D, int DIM, int ORDER>
+__global__ __launch_bounds__(ADJ_NT) void adj_face_a_kernel(AdjParams a) {
   const StageParams& p = a.sp;
   const int n = (D == 0) ? p.nx : p.ny;           // cells along D
   const int m = (D == 0) ? p.ny : p.nx;           // lines
@@ -68,10 +111,12 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
   int fc, l;                                       // face fc lies between cells fc-1 and fc
   if (D == 0) { fc = (int)(f % (n + 1)); l = (int)(f / (n + 1)); }
   else { fc = (int)(f / m); l = (int)(f % m); }
-  double* out = (D == 0) ? a.fbx : a.fby;
-  const long long nfs = (D == 0) ? a.nfx : a.nfy;
   const double inv_h = (D == 0) ? p.inv_dx : p.inv_dy;
   const double mc = a.mu_coef * a.dt;
+  const long long fo = (D == 0) ? (long long)l * (n + 1) + fc : (long long)fc * m + l;
+  double* rl = a.side + fo;
+  double* rr = a.side + nf + fo;
+  const long long ns = a.nside;
 
   // flux adjoint from the two adjacent interior cells
   double Fb[14];
@@ -88,38 +133,85 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
       any = any || (Fb[v] != 0.0);
     }
   }
-  double WLb[14], WRb[14];
+  if (!any) {
 #pragma unroll
-  for (int v = 0; v < 14; ++v) { WLb[v] = 0.0; WRb[v] = 0.0; }
-  if (any) {
-    double WL[14], WR[14];
-    if constexpr (ORDER == 2) {
-      double A[14], B[14], C[14], E[14];
-      line_prims<D>(p, fc - 2, l, A);
-      line_prims<D>(p, fc - 1, l, B);
-      line_prims<D>(p, fc, l, C);
-      line_prims<D>(p, fc + 1, l, E);
-      face_state<Sys14>(A, B, C, forward_phi(p, A, B, C), 1.0, WL);
-      face_state<Sys14>(B, C, E, forward_phi(p, B, C, E), -1.0, WR);
-    } else {
-      line_prims<D>(p, fc - 1, l, WL);
-      line_prims<D>(p, fc, l, WR);
-    }
-    Adj14::face_flux_vjp<D>(WL, WR, p.sigma_lim, p.kws, p.flux, Fb, WLb, WRb);
+    for (int k = 14; k < 44; ++k) { rl[k * ns] = 0.0; rr[k * ns] = 0.0; }
+    return;
   }
-  // face index in the stored layout: x faces row-major (fc fastest), y faces fc-major
-  const long long fo = (D == 0) ? (long long)l * (n + 1) + fc : (long long)fc * m + l;
+  double WL[14], WR[14];
+  if constexpr (ORDER == 2) {
+    double A[14], B[14], C[14], E[14];
+    const long long eB = ext_idx<D, DIM>(a, fc - 1, l), eC = ext_idx<D, DIM>(a, fc, l);
+    const long long st = (D == 0) ? 1 : a.epitch;
+    get_w(a, eB - st, A);
+    get_w(a, eB, B);
+    get_w(a, eC, C);
+    get_w(a, eC + st, E);
+    const double phL = (D == 0) ? a.phix[eB] : a.phiy[eB];
+    const double phR = (D == 0) ? a.phix[eC] : a.phiy[eC];
+    face_state<Sys14>(A, B, C, phL, 1.0, WL);
+    face_state<Sys14>(B, C, E, phR, -1.0, WR);
+  } else {
+    get_w(a, ext_idx<D, DIM>(a, fc - 1, l), WL);
+    get_w(a, ext_idx<D, DIM>(a, fc, l), WR);
+  }
+  double UL[14], FL[14], UR[14], FR[14], lminL, lmaxL, lminR, lmaxR;
+  Sys14::face_terms<D>(WL, p.sigma_lim, p.kws, UL, FL, lminL, lmaxL);
+  Sys14::face_terms<D>(WR, p.sigma_lim, p.kws, UR, FR, lminR, lmaxR);
+  double ULb[14], FLb[14], URb[14], FRb[14], lminLb, lmaxLb, lminRb, lmaxRb;
+  Adj14::interface_vjp(UL, FL, lminL, lmaxL, UR, FR, lminR, lmaxR, p.flux, Fb, ULb, FLb, lminLb,
+                       lmaxLb, URb, FRb, lminRb, lmaxRb);
 #pragma unroll
   for (int v = 0; v < 14; ++v) {
-    out[v * nfs + fo] = WLb[v];
-    out[(14 + v) * nfs + fo] = WRb[v];
+    rl[v * ns] = WL[v];
+    rl[(14 + v) * ns] = ULb[v];
+    rl[(28 + v) * ns] = FLb[v];
+    rr[v * ns] = WR[v];
+    rr[(14 + v) * ns] = URb[v];
+    rr[(28 + v) * ns] = FRb[v];
   }
+  rl[42 * ns] = lminLb; rl[43 * ns] = lmaxLb;
+  rr[42 * ns] = lminRb; rr[43 * ns] = lmaxRb;
+}
+
+template <int D>
+__global__ __launch_bounds__(ADJ_NT) void adj_face_b_kernel(AdjParams a) {
+  const StageParams& p = a.sp;
+  const long long nf = (D == 0) ? a.nfx : a.nfy;
+  const long long r = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  if (r >= 2 * nf) return;
+  const long long ns = a.nside;
+  const double* rec = a.side + r;
+  double Ub[14], Fb[14];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < 14; ++v) {
+    Ub[v] = rec[(14 + v) * ns];
+    Fb[v] = rec[(28 + v) * ns];
+    any = any || Ub[v] != 0.0 || Fb[v] != 0.0;
+  }
+  const double lminb = rec[42 * ns], lmaxb = rec[43 * ns];
+  any = any || lminb != 0.0 || lmaxb != 0.0;
+  double Wb[14];
+#pragma unroll
+  for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
+  if (any) {
+    double W[14];
+#pragma unroll
+    for (int v = 0; v < 14; ++v) W[v] = rec[v * ns];
+    Adj14::face_terms_vjp<D>(W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
+  }
+  // face-state adjoints: [0,14) of the face's left state, [14,28) of its right state
+  double* out = (D == 0) ? a.fbx : a.fby;
+  const long long side = r / nf, fo = r % nf;
+#pragma unroll
+  for (int v = 0; v < 14; ++v) out[(side * 14 + v) * nf + fo] = Wb[v];
 }
 
 // ------------------------------------------------------------------ 2. extended cells
 // adjoint of the primitive state of cell c (line l, direction D) through the reconstruction
 // of the stencil cells c-1, c, c+1
-template <int D, int ORDER>
+template <int D, int DIM, int ORDER>
 __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, double* Wb) {
   const StageParams& p = a.sp;
   const int n = (D == 0) ? p.nx : p.ny;
@@ -142,10 +234,15 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
     }
   } else {
     // stencil cells k = c-1, c, c+1 with face states (k in [-1, n]); their stencils span
-    // cells c-2 .. c+2
+    // cells c-2 .. c+2, of which those in [-2, n+1] are stored
+    const long long st = (D == 0) ? 1 : a.epitch;
+    const long long e0 = ext_idx<D, DIM>(a, c, l);
     double S[5][14];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) line_prims<D>(p, c - 2 + q, l, S[q]);
+    for (int q = 0; q < 5; ++q) {
+      const int cq = c - 2 + q;
+      if (cq >= -2 && cq <= n + 1) get_w(a, e0 + (q - 2) * st, S[q]);
+    }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const int k = c - 1 + r;
@@ -159,8 +256,9 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
         any = any || Op[v] != 0.0 || Om[v] != 0.0;
       }
       if (!any) continue;
-      int vstar;
-      double phi = Adj14::limiter_select(S[r], S[r + 1], S[r + 2], p.limiter, p.fallback, vstar);
+      const long long ek = e0 + (r - 1) * st;
+      const double phi = (D == 0) ? a.phix[ek] : a.phiy[ek];
+      const int vstar = (D == 0) ? a.vsx[ek] : a.vsy[ek];
       // cell c is the stencil's Wp (r = 0), Wc (r = 1) or Wm (r = 2)
       Adj14::recon_vjp_role(2 - r, S[r], S[r + 1], S[r + 2], phi, vstar, p.limiter, Op, Om, Wb);
     }
@@ -180,8 +278,10 @@ __global__ __launch_bounds__(ADJ_NT) void adj_cell_kernel(AdjParams a) {
 #pragma unroll
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
   const bool in_i = i >= 0 && i < p.nx, in_j = j >= 0 && j < p.ny;
-  if (in_j) gather_line<0, ORDER>(a, i, j, Wb);
-  if (DIM == 2 && in_i) gather_line<1, ORDER>(a, j, i, Wb);
+  if (in_j) gather_line<0, DIM, ORDER>(a, i, j, Wb);
+  if constexpr (DIM == 2) {
+    if (in_i) gather_line<1, DIM, ORDER>(a, j, i, Wb);
+  }
 #pragma unroll
   for (int v = 0; v < 14; ++v) a.wb[v * a.eplane + e] = Wb[v];
 }
@@ -349,18 +449,19 @@ int adjoint_update_blocks(int nx, int ny) {
 
 template <int DIM, int ORDER>
 static hipError_t launch_adj_t(AdjParams& a, hipStream_t s) {
-  const StageParams& p = a.sp;
-  int gx = (int)((a.nfx + ADJ_NT - 1) / ADJ_NT);
-  hipLaunchKernelGGL((adj_face_kernel<0, ORDER>), dim3(gx), dim3(ADJ_NT), 0, s, a);
+  auto blocks = [](long long n) { return dim3((unsigned)((n + ADJ_NT - 1) / ADJ_NT)); };
+  hipLaunchKernelGGL((adj_prim_kernel<DIM>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
+  if constexpr (ORDER == 2)
+    hipLaunchKernelGGL((adj_limiter_kernel<DIM>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_face_a_kernel<0, DIM, ORDER>), blocks(a.nfx), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_face_b_kernel<0>), blocks(2 * a.nfx), dim3(ADJ_NT), 0, s, a);
   if constexpr (DIM == 2) {
-    int gy = (int)((a.nfy + ADJ_NT - 1) / ADJ_NT);
-    hipLaunchKernelGGL((adj_face_kernel<1, ORDER>), dim3(gy), dim3(ADJ_NT), 0, s, a);
+    hipLaunchKernelGGL((adj_face_a_kernel<1, DIM, ORDER>), blocks(a.nfy), dim3(ADJ_NT), 0, s, a);
+    hipLaunchKernelGGL((adj_face_b_kernel<1>), blocks(2 * a.nfy), dim3(ADJ_NT), 0, s, a);
   }
-  int ge = (int)((a.eplane + ADJ_NT - 1) / ADJ_NT);
-  hipLaunchKernelGGL((adj_cell_kernel<DIM, ORDER>), dim3(ge), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_cell_kernel<DIM, ORDER>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL((adj_update_kernel<DIM>), dim3(a.n_upd_blocks), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(ADJ_NT), 0, s, a.part, a.n_upd_blocks, a.grad);
-  (void)p;
   return hipGetLastError();
 }
 

@@ -905,19 +905,17 @@ struct Adj14 {
     return cdotb;
   }
 
-  // face_flux<d> (HLL or Rusanov of two face states): WLb, WRb += ...
-  template <int d, class T>
-  MX_HD static void face_flux_vjp(const T* WL, const T* WR, T sigma_lim, T kws, int flux_kind,
-                                  const T* Fhb, T* WLb, T* WRb) {
+  // Reverse of the HLL / Rusanov combination of two face states' (U, F, lambda_min,
+  // lambda_max): given Fhb, sets the adjoints of both sides' U, F and speeds (overwritten).
+  template <class T>
+  MX_HD static void interface_vjp(const T* UL, const T* FL, T lminL, T lmaxL, const T* UR,
+                                  const T* FR, T lminR, T lmaxR, int flux_kind, const T* Fhb,
+                                  T* ULb, T* FLb, T& lminLb, T& lmaxLb, T* URb, T* FRb, T& lminRb,
+                                  T& lmaxRb) {
     constexpr int NV = 14;
-    T UL[NV], FL[NV], UR[NV], FR[NV];
-    T lminL, lmaxL, lminR, lmaxR;
-    S::face_terms<d>(WL, sigma_lim, kws, UL, FL, lminL, lmaxL);
-    S::face_terms<d>(WR, sigma_lim, kws, UR, FR, lminR, lmaxR);
-    T ULb[NV], FLb[NV], URb[NV], FRb[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) { ULb[v] = FLb[v] = URb[v] = FRb[v] = T(0); }
-    T lminLb = T(0), lmaxLb = T(0), lminRb = T(0), lmaxRb = T(0);
+    lminLb = lmaxLb = lminRb = lmaxRb = T(0);
     if (flux_kind == 0) {
       T SL = tmin(lminL, lminR), SR = tmax(lmaxL, lmaxR);
       if (SL >= T(0)) {
@@ -948,7 +946,7 @@ struct Adj14 {
         T db = -invb * inv * inv;  // d/d(SR - SL)
         SRb += db;
         SLb -= db;
-        // SL = min(lminL, lminR), SR = max(lmaxL, lmaxR): the taken branch
+        // SL = min(lminL, lminR), SR = max(lmaxL, lmaxR): the branch the forward took
         if (lminL < lminR) lminLb += SLb; else lminRb += SLb;
         if (lmaxL > lmaxR) lmaxLb += SRb; else lmaxRb += SRb;
       }
@@ -965,7 +963,7 @@ struct Adj14 {
         URb[v] -= T(0.5) * am * Fhb[v];
         ULb[v] += T(0.5) * am * Fhb[v];
       }
-      // am = max(max(|lminL|, |lmaxL|), max(|lminR|, |lmaxR|)): the taken branch
+      // am = max(max(|lminL|, |lmaxL|), max(|lminR|, |lmaxR|)): the branch taken
       if (mL > mR) {
         if (aL1 > aL2) lminLb += amb * (lminL < T(0) ? T(-1) : T(1));
         else lmaxLb += amb * (lmaxL < T(0) ? T(-1) : T(1));
@@ -974,6 +972,21 @@ struct Adj14 {
         else lmaxRb += amb * (lmaxR < T(0) ? T(-1) : T(1));
       }
     }
+  }
+
+  // face_flux<d> (HLL or Rusanov of two face states): WLb, WRb += ...
+  template <int d, class T>
+  MX_HD static void face_flux_vjp(const T* WL, const T* WR, T sigma_lim, T kws, int flux_kind,
+                                  const T* Fhb, T* WLb, T* WRb) {
+    constexpr int NV = 14;
+    T UL[NV], FL[NV], UR[NV], FR[NV];
+    T lminL, lmaxL, lminR, lmaxR;
+    S::face_terms<d>(WL, sigma_lim, kws, UL, FL, lminL, lmaxL);
+    S::face_terms<d>(WR, sigma_lim, kws, UR, FR, lminR, lmaxR);
+    T ULb[NV], FLb[NV], URb[NV], FRb[NV];
+    T lminLb, lmaxLb, lminRb, lmaxRb;
+    interface_vjp(UL, FL, lminL, lmaxL, UR, FR, lminR, lmaxR, flux_kind, Fhb, ULb, FLb, lminLb,
+                  lmaxLb, URb, FRb, lminRb, lmaxRb);
     face_terms_vjp<d>(WL, sigma_lim, kws, ULb, FLb, lminLb, lmaxLb, WLb);
     face_terms_vjp<d>(WR, sigma_lim, kws, URb, FRb, lminRb, lmaxRb, WRb);
   }
@@ -1035,8 +1048,16 @@ struct Adj14 {
       else Wb[v] -= abb;
     }
     if (vstar >= 0) {
-      T a = Wc[vstar] - Wm[vstar];
-      T b = Wp[vstar] - Wc[vstar];
+      // the selected variable's jumps, picked without a runtime array index (keeps the
+      // arrays in registers)
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (v == vstar) {
+          a = Wc[v] - Wm[v];
+          b = Wp[v] - Wc[v];
+        }
+      }
       T dpa, dpb;
       if (kind == 0) {
         T aa = tabs(a), ab = tabs(b), s = aa + ab;
@@ -1053,9 +1074,10 @@ struct Adj14 {
       }
       T ab_ = phib * dpa, bb_ = phib * dpb;
       // a = Wc - Wm, b = Wp - Wc
-      if (role == 1) Wb[vstar] += ab_ - bb_;
-      else if (role == 0) Wb[vstar] -= ab_;
-      else Wb[vstar] += bb_;
+      const T add = (role == 1) ? ab_ - bb_ : ((role == 0) ? -ab_ : bb_);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (v == vstar) Wb[v] += add;
     }
   }
 

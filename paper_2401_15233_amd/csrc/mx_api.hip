@@ -50,6 +50,12 @@ struct TapeState {
   double* fbx = nullptr;
   double* fby = nullptr;
   double* wb = nullptr;
+  double* wext = nullptr;
+  double* phix = nullptr;
+  double* phiy = nullptr;
+  int* vsx = nullptr;
+  int* vsy = nullptr;
+  double* side = nullptr;
   double* part = nullptr;
   double* grad = nullptr;
   DevCtrl* actrl = nullptr;              // control block of the replayed stages
@@ -78,6 +84,7 @@ struct maxent_solver {
   long long prof_n = 0;
   BatchState* batch = nullptr;
   TapeState* tape = nullptr;
+  int adj_mode = MAXENT_ADJ_EXACT;
   std::string err;
 };
 
@@ -149,8 +156,10 @@ static void free_tape(maxent_solver* s) {
   for (double* p : t->ckpt) if (p) (void)hipFree(p);
   for (double* p : t->seg) if (p) (void)hipFree(p);
   for (double* p : t->lam) if (p) (void)hipFree(p);
-  double* bufs[] = {t->d_dt, t->fbx, t->fby, t->wb, t->part, t->grad};
+  double* bufs[] = {t->d_dt, t->fbx, t->fby, t->wb, t->wext, t->phix, t->phiy, t->side, t->part, t->grad};
   for (double* p : bufs) if (p) (void)hipFree(p);
+  if (t->vsx) (void)hipFree(t->vsx);
+  if (t->vsy) (void)hipFree(t->vsy);
   if (t->actrl) (void)hipFree(t->actrl);
   delete t;
   s->tape = nullptr;
@@ -492,6 +501,14 @@ extern "C" int maxent_record(maxent_solver* s, int checkpoint_every, int max_ste
   return MAXENT_OK;
 }
 
+extern "C" int maxent_set_adjoint_mode(maxent_solver* s, int mode) {
+  if (!s) return MAXENT_E_INVAL;
+  if (mode != MAXENT_ADJ_EXACT && mode != MAXENT_ADJ_FROZEN_LIMITER)
+    return fail(s, MAXENT_E_INVAL, "unknown adjoint mode");
+  s->adj_mode = mode;
+  return MAXENT_OK;
+}
+
 extern "C" int maxent_set_inflow(maxent_solver* s, double mach, double rho) {
   if (!s) return MAXENT_E_INVAL;
   if (!(mach > 0) || !(rho > 0) || !std::isfinite(mach) || !std::isfinite(rho))
@@ -533,6 +550,12 @@ static hipError_t adjoint_workspace(maxent_solver* s) {
   if (e == hipSuccess) e = hipMalloc(&t->fbx, (size_t)28 * nfx * sizeof(double));
   if (e == hipSuccess && nfy) e = hipMalloc(&t->fby, (size_t)28 * nfy * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&t->wb, (size_t)14 * eplane * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&t->wext, (size_t)14 * eplane * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&t->phix, (size_t)eplane * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&t->phiy, (size_t)eplane * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&t->vsx, (size_t)eplane * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&t->vsy, (size_t)eplane * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&t->side, (size_t)44 * 2 * std::max(nfx, nfy) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&t->part, (size_t)3 * nb * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&t->grad, 3 * sizeof(double));
   for (auto& p : t->lam)
@@ -554,8 +577,11 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
     // leave the tape usable for the forward run; drop the partial workspace
     for (auto& p : t->seg) { if (p) (void)hipFree(p); p = nullptr; }
     for (auto& p : t->lam) { if (p) (void)hipFree(p); p = nullptr; }
-    double** bufs[] = {&t->fbx, &t->fby, &t->wb, &t->part, &t->grad};
+    double** bufs[] = {&t->fbx, &t->fby, &t->wb, &t->wext, &t->phix, &t->phiy, &t->side, &t->part,
+                       &t->grad};
     for (double** p : bufs) { if (*p) (void)hipFree(*p); *p = nullptr; }
+    int** ibufs[] = {&t->vsx, &t->vsy};
+    for (int** p : ibufs) { if (*p) (void)hipFree(*p); *p = nullptr; }
     if (t->actrl) (void)hipFree(t->actrl);
     t->actrl = nullptr;
     t->seg.clear();
@@ -588,6 +614,14 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   a.nfx = (long long)(nx + 1) * ny;
   a.nfy = dim == 2 ? (long long)nx * (ny + 1) : 0;
   a.wb = t->wb;
+  a.wext = t->wext;
+  a.phix = t->phix;
+  a.phiy = t->phiy;
+  a.vsx = t->vsx;
+  a.vsy = t->vsy;
+  a.side = t->side;
+  a.nside = 2 * std::max(a.nfx, a.nfy);
+  a.frozen_limiter = s->adj_mode == MAXENT_ADJ_FROZEN_LIMITER ? 1 : 0;
   a.epitch = nx + 4;
   a.eplane = (long long)(nx + 4) * (dim == 2 ? ny + 4 : 1);
   a.part = t->part;

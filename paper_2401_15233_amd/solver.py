@@ -22,13 +22,15 @@ INTEGRATOR = {'fe': 0, 'ssprk2': 1, 'midpoint': 2}
 TAU_MODE = {'local': 0, 'const': 1}
 REPR = {'primitive': 0, 'conserved': 1, 'sigma': 2}
 PRECISION = {'fp64': 0, 'mixed': 2}
+ADJOINT_MODE = {'exact': 0, 'frozen_limiter': 1}
 
 EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_moments',
             'maxent_num_vars', 'maxent_get_info', 'maxent_destroy', 'maxent_last_error',
             'maxent_abi_version', 'maxent_set_profiling', 'maxent_get_profile',
             'maxent_create_batch', 'maxent_step_batch', 'maxent_set_batch_launch',
             'maxent_get_batch_launch', 'maxent_autotune_batch', 'maxent_record',
-            'maxent_set_inflow', 'maxent_step_adjoint', 'maxent_tape_info')
+            'maxent_set_inflow', 'maxent_step_adjoint', 'maxent_tape_info',
+            'maxent_set_adjoint_mode')
 
 
 class MaxentError(RuntimeError):
@@ -125,6 +127,7 @@ def load_library(path=LIB_PATH):
     L.maxent_record.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.maxent_set_inflow.argtypes = [vp, ctypes.c_double, ctypes.c_double]
     L.maxent_tape_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), vp]
+    L.maxent_set_adjoint_mode.argtypes = [vp, ctypes.c_int]
     L.maxent_step_adjoint.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_double)]
     _lib = L
@@ -271,6 +274,10 @@ class MaxEntSolver:
     def set_inflow(self, mach, rho):
         self._check(self._lib.maxent_set_inflow(self._h, float(mach), float(rho)))
         self.problem.jet_mach, self.problem.jet_rho = float(mach), float(rho)
+
+    def set_adjoint_mode(self, mode):
+        """'exact' (default) or 'frozen_limiter'."""
+        self._check(self._lib.maxent_set_adjoint_mode(self._h, ADJOINT_MODE[mode]))
 
     def tape(self):
         """Time steps of the recorded steps (NumPy array)."""

@@ -173,6 +173,45 @@ def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0, perturb=PERT
     return base, spread, t, n, nspread
 
 
+def oracle_with_flux_rounding_spread(kw, W0, tau_ref, nsteps, trials=2, seed=0, rel=2.0 ** -24):
+    """The oracle's L1 change per moment when every physical flux component and every wave
+    speed it evaluates carries one random relative rounding of size rel (2^-24: one FP32
+    rounding), with the oracle's arithmetic otherwise untouched: how far a correct
+    computation whose fluxes are rounded to single precision at each evaluation can move.
+    Returns (base, spread)."""
+    s = to_setup(kw)
+    U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
+    if s.dim == 1:
+        U0 = U0.reshape(U0.shape[0], -1)
+    base, _, _ = sc.run(U0, s, tau_ref, nsteps=nsteps)
+    rng = np.random.default_rng(seed)
+    names = ('flux14', 'wavespeeds14') if s.system == 14 else ('flux5', 'wavespeeds5')
+    orig = {k: getattr(sc, k) for k in names}
+
+    def rnd(a):
+        a = np.asarray(a, dtype=float)
+        return a * (1.0 + rng.choice([-1.0, 1.0], a.shape) * rel)
+
+    def flux(*a, **k):
+        return rnd(orig[names[0]](*a, **k))
+
+    def speeds(*a, **k):
+        lmin, lmax = orig[names[1]](*a, **k)
+        return rnd(lmin), rnd(lmax)
+
+    spread = np.zeros(base.shape[0])
+    try:
+        setattr(sc, names[0], flux)
+        setattr(sc, names[1], speeds)
+        for _ in range(trials):
+            out, _, _ = sc.run(U0, s, tau_ref, nsteps=nsteps)
+            spread = np.maximum(spread, np.abs(out - base).reshape(base.shape[0], -1).sum(1))
+    finally:
+        for k, f in orig.items():
+            setattr(sc, k, f)
+    return base, spread
+
+
 # ---------------------------------------------------------------- adjoint references
 def oracle_objective(kw, U0, weights, nsteps, dt, tau_ref, mach=None, rho=None):
     """J = sum(weights * U_n) after nsteps oracle steps of fixed dt from the conserved U0

@@ -3,11 +3,15 @@ near the Junk subspace and the realizability boundary; FP64 state, reconstructio
 dissipation and update) against the FP64 oracle.  The error is stated per moment in L1,
 relative to the oracle's L1 norm; conservation stays at FP64 round-off.
 
-Bar: L1 error <= max(2e-6, 10 x the oracle's own L1 change when its input is perturbed by
-+-2^-24 relative (single-precision rounding)).  On well-conditioned flows (jets from rest,
-Sod) that spread is ~1e-7 and the bar is 2e-6; the developed crossed-jets field is so
-sensitive (common-limiter switching in the beam tails, near-Junk wave speeds) that an
-FP32-sized input perturbation moves the oracle itself by ~1e-2 in L1."""
+Bar: L1 error <= max(2e-6, 10 x spread), where the spread is the larger of two changes of
+the oracle's own L1 result (computed by the oracle alone): (a) when its input is perturbed
+by +-2^-24 relative, and (b) when every physical flux and wave speed it evaluates carries
+one random +-2^-24 relative rounding -- what single-precision flux evaluation does to an
+otherwise exact computation at every stage.  On smooth flows both are ~1e-7 and the bar is
+the floor; the developed crossed-jets field is so sensitive (common-limiter switching in the
+beam tails, near-Junk wave speeds) that an FP32-sized perturbation moves the oracle itself by
+~1e-2 in L1; the jets entering a 1e-3 background respond to per-stage flux rounding at the
+front (b) far more than to an input perturbation (a)."""
 import numpy as np
 import pytest
 
@@ -50,13 +54,15 @@ def test_mixed_jets_l1_error_against_fp64_oracle(gpu_lib, field):
     Um, info = run(gpu_lib, dict(kw, precision='mixed'), W0, n, tau_ref=TAU_JET)
     base, spread, t, no, _ = ob.oracle_with_l1_spread(kw, W0, 0.0, TAU_JET, trials=2,
                                                       perturb=FP32_PERTURB, nsteps=n)
+    _, fspread = ob.oracle_with_flux_rounding_spread(kw, W0, TAU_JET, n, trials=2)
+    spread = np.maximum(spread, fspread)
     b1 = np.maximum(np.abs(base).reshape(14, -1).sum(1), 1e-300)
     err = l1_rel(Um, base)
     sp = spread / b1
     frac = info['n_fp64_states'] / max(info['n_face_states'], 1)
     print(f'mixed jets {field} {n} steps: L1 relative error per moment '
-          f'{np.array2string(err, precision=1)}; oracle FP32-perturbation L1 spread '
-          f'{np.array2string(sp, precision=1)}; FP64 re-evaluated face states {frac:.4f}',
+          f'{np.array2string(err, precision=1)}; oracle FP32-rounding L1 spread '
+          f'{np.array2string(sp, precision=1, floatmode="maxprec_equal")}; FP64 re-evaluated face states {frac:.4f}',
           flush=True)
     assert info['n_face_states'] > 0
     assert np.all(err <= np.maximum(L1_FLOOR, 10 * sp))
@@ -70,6 +76,8 @@ def test_mixed_sod14_l1_error_against_fp64_oracle(gpu_lib):
     Um, info = run(gpu_lib, dict(kw, precision='mixed'), W0, 100, tau_ref=tau)
     base, spread, t, n, _ = ob.oracle_with_l1_spread(kw, W0, 0.0, tau, trials=2,
                                                      perturb=FP32_PERTURB, nsteps=100)
+    _, fspread = ob.oracle_with_flux_rounding_spread(kw, W0, tau, 100, trials=2)
+    spread = np.maximum(spread, fspread)
     b1 = np.maximum(np.abs(base).reshape(14, -1).sum(1), 1e-300)
     err = l1_rel(Um, base)
     print(f'mixed sod14 100 steps: L1 relative error {np.array2string(err, precision=1)}; '
