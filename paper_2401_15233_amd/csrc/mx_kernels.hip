@@ -103,13 +103,18 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
     for (int v = 0; v < NV; ++v) W[v] = sW[v * NL + c];
   };
 
-  // 2. common limiter factors
+  // 2. common limiter factors, x and y items in one sweep (542 items on 256 threads take
+  // three rounds; two separate loops would take four)
   int nfb = 0;
   if constexpr (ORDER == 2) {
-    for (int c = t; c < NPX; c += NT) {
-      int ti = c % (TX + 2) - 1, tj = c / (TX + 2);
+    constexpr int NPT = (DIM == 2) ? NPX + NPY : NPX;
+    for (int c = t; c < NPT; c += NT) {
+      const bool isx = c < NPX;
+      int ti, tj, di, dj;
+      if (isx) { ti = c % (TX + 2) - 1; tj = c / (TX + 2); di = 1; dj = 0; }
+      else { const int cy = c - NPX; ti = cy % TX; tj = cy / TX - 1; di = 0; dj = 1; }
       double Wm[NV], Wc[NV], Wp[NV];
-      lds(ti - 1, tj, Wm); lds(ti, tj, Wc); lds(ti + 1, tj, Wp);
+      lds(ti - di, tj - dj, Wm); lds(ti, tj, Wc); lds(ti + di, tj + dj, Wp);
       double phi = limiter_factor<SYS>(Wm, Wc, Wp, p.limiter);
       if (p.fallback && phi > 0.0) {
         double Wf[NV];
@@ -119,30 +124,12 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         ok = ok && SYS::admissible(Wf);
         if (!ok) {
           phi = 0.0;
-          if (ti >= 0 && ti < TX && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
+          const bool own = isx ? (ti >= 0 && ti < TX) : (tj >= 0 && tj < TY);
+          if (own && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
         }
       }
-      sPx[c] = phi;
-    }
-    if constexpr (DIM == 2) {
-      for (int c = t; c < NPY; c += NT) {
-        int ti = c % TX, tj = c / TX - 1;
-        double Wm[NV], Wc[NV], Wp[NV];
-        lds(ti, tj - 1, Wm); lds(ti, tj, Wc); lds(ti, tj + 1, Wp);
-        double phi = limiter_factor<SYS>(Wm, Wc, Wp, p.limiter);
-        if (p.fallback && phi > 0.0) {
-          double Wf[NV];
-          face_state<SYS>(Wm, Wc, Wp, phi, 1.0, Wf);
-          bool ok = SYS::admissible(Wf);
-          face_state<SYS>(Wm, Wc, Wp, phi, -1.0, Wf);
-          ok = ok && SYS::admissible(Wf);
-          if (!ok) {
-            phi = 0.0;
-            if (tj >= 0 && tj < TY && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
-          }
-        }
-        sPy[c] = phi;
-      }
+      if (isx) sPx[c] = phi;
+      else sPy[c - NPX] = phi;
     }
     __syncthreads();
   }

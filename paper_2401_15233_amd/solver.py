@@ -98,6 +98,10 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f'{path} is not built; run `python -m paper_2401_15233_amd.build`')
+    # PyTorch-ROCm ships its own HIP runtime under the same soname as the system one: load
+    # torch first so that the library binds to that runtime.  Loading the library first would
+    # put a second HIP runtime into the process, and device discovery then fails.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     L.maxent_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Numerics), vp,
