@@ -27,6 +27,7 @@
 // No atomics: the result is bitwise reproducible.  Faces whose flux adjoint is exactly zero
 // (outside the adjoint's domain of dependence) skip the closure reverse.
 #include "mx_internal.hpp"
+#include "mx_adjoint_params.hpp"
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
 #include "mx_bc.hpp"
@@ -35,6 +36,19 @@
 namespace mx {
 
 constexpr int ADJ_NT = 256;
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-robin to the 8 XCDs;
+// give each XCD a contiguous range of blocks so that the neighbour data these gathers re-read
+// stays in that XCD's L2
+__device__ __forceinline__ long long xcd_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned per = (nb + 7) / 8;
+  const unsigned full = nb % 8 == 0 ? 8 : nb % 8;   // XCDs that receive `per` blocks
+  const unsigned x = b % 8, k = b / 8;
+  // blocks of XCD x in dealing order get the contiguous range starting at its offset
+  const unsigned off = (x < full) ? x * per : full * per + (x - full) * (per - 1);
+  return (long long)(off + k);
+}
 
 __device__ __forceinline__ long long ucell(const StageParams& p, int i, int j) {
   return (long long)j * p.pitch + i;
@@ -55,7 +69,7 @@ __device__ __forceinline__ void get_w(const AdjParams& a, long long e, double* W
 // ------------------------------------------------------------------ 0. prep
 template <int DIM>
 __global__ __launch_bounds__(ADJ_NT) void adj_prim_kernel(AdjParams a) {
-  const long long e = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  const long long e = xcd_block() * ADJ_NT + threadIdx.x;
   if (e >= a.eplane) return;
   const int i = (int)(e % a.epitch) - 2;
   const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
@@ -68,7 +82,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_prim_kernel(AdjParams a) {
 template <int DIM>
 __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
   const StageParams& p = a.sp;
-  const long long e = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  const long long e = xcd_block() * ADJ_NT + threadIdx.x;
   if (e >= a.eplane) return;
   const int i = (int)(e % a.epitch) - 2;
   const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
@@ -106,7 +120,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_a_kernel(AdjParams a) {
   const int n = (D == 0) ? p.nx : p.ny;           // cells along D
   const int m = (D == 0) ? p.ny : p.nx;           // lines
   const long long nf = (long long)(n + 1) * m;
-  const long long f = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  const long long f = xcd_block() * ADJ_NT + threadIdx.x;
   if (f >= nf) return;
   int fc, l;                                       // face fc lies between cells fc-1 and fc
   if (D == 0) { fc = (int)(f % (n + 1)); l = (int)(f / (n + 1)); }
@@ -178,7 +192,7 @@ template <int D>
 __global__ __launch_bounds__(ADJ_NT) void adj_face_b_kernel(AdjParams a) {
   const StageParams& p = a.sp;
   const long long nf = (D == 0) ? a.nfx : a.nfy;
-  const long long r = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  const long long r = xcd_block() * ADJ_NT + threadIdx.x;
   if (r >= 2 * nf) return;
   const long long ns = a.nside;
   const double* rec = a.side + r;
@@ -233,16 +247,11 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
       for (int v = 0; v < 14; ++v) Wb[v] += fb[v * nfs + fidx(c + 1)];
     }
   } else {
-    // stencil cells k = c-1, c, c+1 with face states (k in [-1, n]); their stencils span
-    // cells c-2 .. c+2, of which those in [-2, n+1] are stored
+    // stencil cells k = c-1, c, c+1 with face states (k in [-1, n]); each stencil's three
+    // cells are read when needed (re-reads hit L2; holding all five cells would cost 140
+    // registers)
     const long long st = (D == 0) ? 1 : a.epitch;
     const long long e0 = ext_idx<D, DIM>(a, c, l);
-    double S[5][14];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int cq = c - 2 + q;
-      if (cq >= -2 && cq <= n + 1) get_w(a, e0 + (q - 2) * st, S[q]);
-    }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const int k = c - 1 + r;
@@ -257,10 +266,14 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
       }
       if (!any) continue;
       const long long ek = e0 + (r - 1) * st;
+      double Sm[14], Sc[14], Sp[14];
+      get_w(a, ek - st, Sm);
+      get_w(a, ek, Sc);
+      get_w(a, ek + st, Sp);
       const double phi = (D == 0) ? a.phix[ek] : a.phiy[ek];
       const int vstar = (D == 0) ? a.vsx[ek] : a.vsy[ek];
       // cell c is the stencil's Wp (r = 0), Wc (r = 1) or Wm (r = 2)
-      Adj14::recon_vjp_role(2 - r, S[r], S[r + 1], S[r + 2], phi, vstar, p.limiter, Op, Om, Wb);
+      Adj14::recon_vjp_role(2 - r, Sm, Sc, Sp, phi, vstar, p.limiter, Op, Om, Wb);
     }
   }
 }
@@ -268,7 +281,7 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
 template <int DIM, int ORDER>
 __global__ __launch_bounds__(ADJ_NT) void adj_cell_kernel(AdjParams a) {
   const StageParams& p = a.sp;
-  const long long e = (long long)blockIdx.x * ADJ_NT + threadIdx.x;
+  const long long e = xcd_block() * ADJ_NT + threadIdx.x;
   if (e >= a.eplane) return;
   const int ei = (int)(e % a.epitch);
   const int ej = (int)(e / a.epitch);

@@ -9,6 +9,7 @@
 
 #include "../../include/maxent.h"
 #include "mx_internal.hpp"
+#include "mx_adjoint_params.hpp"
 #include "mx_batch.hpp"
 
 using mx::DevCtrl;
