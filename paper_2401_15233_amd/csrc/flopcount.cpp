@@ -104,8 +104,7 @@ static void cell_stage(bool last) {
   Sys14::cons_to_prim(Un, Wn);
   (void)Sys14::admissible(Wn);
   if (last) {
-    CD r = Sys14::cell_lambda<0>(Wn, sl, kws) / CD(1.0 / 2048) +
-           Sys14::cell_lambda<1>(Wn, sl, kws) / CD(1.0 / 2048);
+    CD r = Sys14::cell_rate2d(Wn, sl, kws, CD(1.0 / 2048), CD(1.0 / 2048));
     (void)r;
   }
 }

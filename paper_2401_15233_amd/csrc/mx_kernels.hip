@@ -233,8 +233,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         if constexpr (DIM == 1) {
           rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws);
         } else {
-          rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws) / p.dx +
-                 SYS::template cell_lambda<1>(Wn, p.sigma_lim, p.kws) / p.dy;
+          rate = SYS::cell_rate2d(Wn, p.sigma_lim, p.kws, p.dx, p.dy);
         }
       }
     }
@@ -291,8 +290,7 @@ __global__ __launch_bounds__(256) void cfl_kernel(CflParams p) {
     double r;
     if constexpr (DIM == 1) r = SYS::template cell_lambda<0>(W, p.sigma_lim, p.kws);
     else
-      r = SYS::template cell_lambda<0>(W, p.sigma_lim, p.kws) / p.dx +
-          SYS::template cell_lambda<1>(W, p.sigma_lim, p.kws) / p.dy;
+      r = SYS::cell_rate2d(W, p.sigma_lim, p.kws, p.dx, p.dy);
     rate = fmax(rate, r);
   }
   rate = wave_max(rate);

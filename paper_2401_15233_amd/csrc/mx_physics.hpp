@@ -422,6 +422,18 @@ struct Sys14 {
     return tmax(tabs(lmin), tabs(lmax));
   }
 
+  // 2D CFL rate Lambda_x / dx + Lambda_y / dy of a cell state (one closure core for both
+  // directions; the same values as cell_lambda<0> / dx + cell_lambda<1> / dy)
+  template <class T>
+  MX_HD static T cell_rate2d(const T* W, T sigma_lim, T kws, T dx, T dy) {
+    Core<T> k;
+    core(W, sigma_lim, k);
+    T a, b, c, d;
+    wavespeeds<0>(k, W[1], kws, a, b);
+    wavespeeds<1>(k, W[2], kws, c, d);
+    return tmax(tabs(a), tabs(b)) / dx + tmax(tabs(c), tabs(d)) / dy;
+  }
+
   template <class T> MX_HD static T sigma(const T* W) {
     Core<T> k;
     core(W, T(0), k);

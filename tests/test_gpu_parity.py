@@ -158,6 +158,15 @@ def test_jets_2d_developed_field(gpu_lib):
         assert abs(info['t'] - t) < 1e-12 * t
 
 
+def test_jets_2d_inflated_wave_speeds(gpu_lib):
+    """The benchmark's setting: wave speeds x 1.2 (HLL signal speeds and the CFL step)."""
+    nx, ny = 70, 50
+    kw = dict(JETS, nx=nx, ny=ny, k_ws=1.2)
+    W0 = I.crossed_jets_developed(nx, ny, seed=6)
+    Ug, info, base, t, n = compare('jets 70x50 k_ws 1.2, 3 steps', gpu_lib, kw, W0, 3, tau_ref=TAU_JET)
+    assert abs(info['t'] - t) < 1e-12 * t
+
+
 def test_jets_2d_from_rest_first_order(gpu_lib):
     nx, ny = 48, 40
     kw = dict(JETS, nx=nx, ny=ny, order=1, integrator='fe', cfl=0.5)
