@@ -67,7 +67,7 @@ template <class T> MX_HD void symadj_vjp(const T* A, const T* C, const T* Cb, T 
 
 template <class T> MX_HD void sqrt_vjp(T x, T y, T yb, T& xb) {
   // y = sqrt(x); derivative 1/(2y), none at y = 0 (clamped or exact zero)
-  if (y > T(0)) xb += yb / (T(2) * y);
+  if (y > T(0)) xb += mdiv(yb, T(2) * y);
 }
 
 // ===================================================================== 14 moments
@@ -78,7 +78,7 @@ struct Adj14 {
   template <class T> MX_HD static void cons_to_prim_vjp(const T* U, const T* Wb_in, T* Ub) {
     // forward, kept
     T rho = U[0];
-    T ir = T(1) / rho;
+    T ir = mrcp(rho);
     T u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
     T P[6];
 #pragma unroll
@@ -242,8 +242,8 @@ struct Adj14 {
     // forward, kept
     T rho = W[0];
     T p = (W[4] + W[7] + W[9]) * T(1.0 / 3.0);
-    T irho = T(1) / rho;
-    T ip = T(1) / p;
+    T irho = mrcp(rho);
+    T ip = mrcp(p);
     T c = msqrt(p * irho);
     T ic = msqrt(rho * ip);
     T Ph[6];
@@ -262,7 +262,7 @@ struct Adj14 {
     T t2 = P2[0] + P2[3] + P2[5];
     T C[6];
     T det = symadj(Ph, C);
-    T idet = T(1) / det;
+    T idet = mrcp(det);
     T y[3];
     symv(C, qh, y);
     T z[3] = {y[0] * idet, y[1] * idet, y[2] * idet};
@@ -273,7 +273,7 @@ struct Adj14 {
     bool apos = A >= T(0);
     T num = apos ? (A + sX) : T(2) * D;
     T den = apos ? T(4) * t2 : (sX - A);
-    T sig = num / den;
+    T sig = mdiv(num, den);
     // reverse
     T Phb[6], P2b[6], qhb[3], zb[3];
 #pragma unroll
@@ -282,8 +282,9 @@ struct Adj14 {
     for (int i = 0; i < 3; ++i) { qhb[i] = kb_in.qh[i]; zb[i] = kb_in.z[i]; }
     T rhob = kb_in.rho, cb = kb_in.c, t1b = kb_in.t1, t2b = kb_in.t2;
     T sigb = (sig > sigma_lim) ? kb_in.sb : T(0);  // sigma_bar = max(sigma, sigma_lim)
-    T numb = sigb / den;
-    T denb = -sigb * sig / den;
+    T iden = mrcp(den);
+    T numb = sigb * iden;
+    T denb = -sigb * sig * iden;
     T Ab = T(0), sXb = T(0), Db = T(0);
     if (apos) {
       Ab += numb;
@@ -373,7 +374,7 @@ struct Adj14 {
     T detc = symadj(Cm, Ca);
     T y[3];
     symv(Ca, k.qh, y);
-    T idc = T(1) / detc;
+    T idc = mrcp(detc);
     T w[3] = {y[0] * idc, y[1] * idc, y[2] * idc};
     T P2z[3];
     symv(k.P2, k.z, P2z);
@@ -384,7 +385,7 @@ struct Adj14 {
     T s3 = k.rho * c3;
     T s4 = s3 * k.c;
     T s5 = s4 * k.c;
-    T isb = T(1) / k.sb;
+    T isb = mrcp(k.sb);
     T Pw[3], P2w[3];
     symv(k.Ph, w, Pw);
     symv(k.P2, w, P2w);
@@ -536,9 +537,10 @@ struct Adj14 {
       sqrt_vjp(X, sX, sXb, Xb);
     } else {
       T den = sX - zeta;
-      T h = rest / den;
-      restb += hb / den;
-      T denb = -hb * h / den;
+      T h = mdiv(rest, den);
+      T iden = mrcp(den);
+      restb += hb * iden;
+      T denb = -hb * h * iden;
       sqrt_vjp(X, sX, denb, Xb);
       zetab -= denb;
     }
@@ -584,7 +586,7 @@ struct Adj14 {
     T sB = msqrt(B);
     T Y = B + E * E - T(2) * E * sB;
     T twosw = T(2) * sw;
-    T pref = (a * sw + b) / twosw;
+    T pref = mdiv(a * sw + b, twosw);
     T base = T(4) * sw * sw * Y + qt * qt * T(0.1);
     T zmax = qd + qt * alpha;
     T zmin = -qd + qt * alpha;
@@ -622,9 +624,10 @@ struct Adj14 {
     T Yb = baseb * T(4) * sw * sw;
     qtb += baseb * T(0.2) * qt;
     // pref = (a sw + b) / (2 sw)
-    T ab = prefb * sw / twosw;
-    T bb = prefb / twosw;
-    swb += prefb * (a / twosw - T(2) * pref / twosw);
+    T itw = mrcp(twosw);
+    T ab = prefb * sw * itw;
+    T bb = prefb * itw;
+    swb += prefb * (a - T(2) * pref) * itw;
     // Y = B + E^2 - 2 E sB
     T Bb = Yb;
     Eb += Yb * (T(2) * E - T(2) * sB);
@@ -656,7 +659,7 @@ struct Adj14 {
       T argb = eab * ea;
       lPb += argb * T(1.1);
       Pddb += -argb * T(2) * Pdd;
-      Pddb += lPb / Pdd;
+      Pddb += mdiv(lPb, Pdd);
     }
     // alpha = 0.6 Pdd^2 - 0.38 Pdd + 0.35
     Pddb += alphab * (T(1.2) * Pdd - T(0.38));
@@ -843,7 +846,7 @@ struct Adj14 {
       for (int j = i; j < 3; ++j) Bv[4 + sidx(i, j)] = P[sidx(i, j)] - (i == j ? p : T(0));
 #pragma unroll
     for (int i = 0; i < 3; ++i) Bv[10 + i] = T(2) * Pu[i] + q[i] - T(2) * u[i] * p;
-    Bv[13] = (T(4) * uPu + T(4) * uq + W[13]) - (T(4) * uu * p + T(15) * p * p / rho);
+    Bv[13] = (T(4) * uPu + T(4) * uq + W[13]) - (T(4) * uu * p + mdiv(T(15) * p * p, rho));
     T cdotb = T(0);  // Cb . C
     T itb = T(0);    // adjoint of inv_tau
     T Bb[14];
@@ -862,8 +865,9 @@ struct Adj14 {
     uqb += T(4) * Bb[13];
     Wb[13] += Bb[13];
     uub -= T(4) * p * Bb[13];
-    pb -= Bb[13] * (T(4) * uu + T(30) * p / rho);
-    rhob += Bb[13] * T(15) * p * p / (rho * rho);
+    const T irho = mrcp(rho);
+    pb -= Bb[13] * (T(4) * uu + T(30) * p * irho);
+    rhob += Bb[13] * T(15) * p * p * irho * irho;
     // B10+i = 2 Pu_i + q_i - 2 u_i p
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -882,8 +886,8 @@ struct Adj14 {
       }
     // inv_tau = kappa sqrt(rho p) (local)
     if (local_tau) {
-      rhob += itb * inv_tau / (T(2) * rho);
-      pb += itb * inv_tau / (T(2) * p);
+      rhob += itb * inv_tau * T(0.5) * irho;
+      pb += itb * inv_tau * T(0.5) * mrcp(p);
     }
     // uu, uq, uPu, Pu
 #pragma unroll
@@ -925,7 +929,7 @@ struct Adj14 {
 #pragma unroll
         for (int v = 0; v < NV; ++v) FRb[v] = Fhb[v];
       } else {
-        T inv = T(1) / (SR - SL);
+        T inv = mrcp(SR - SL);
         T SLR = SL * SR;
         T SLb = T(0), SRb = T(0), invb = T(0), SLRb = T(0);
 #pragma unroll
@@ -1014,7 +1018,7 @@ struct Adj14 {
       else { fn = T(2) * a * b; fd = a * a + b * b; var = v; }
       if (fn * den < num * fd) { num = fn; den = fd; vstar = var; }
     }
-    T phi = (den == T(1)) ? num : num / den;
+    T phi = (den == T(1)) ? num : mdiv(num, den);
     if (fallback && phi > T(0)) {
       T Wf[NV];
       face_state<S>(Wm, Wc, Wp, phi, T(1), Wf);
@@ -1062,15 +1066,17 @@ struct Adj14 {
       if (kind == 0) {
         T aa = tabs(a), ab = tabs(b), s = aa + ab;
         // phi = 2 min(|a|, |b|) / (|a| + |b|), the smaller one as the forward's tmin picks it
-        if (aa < ab) { dpa = T(2) * ab / (s * s); dpb = -T(2) * aa / (s * s); }
-        else { dpa = -T(2) * ab / (s * s); dpb = T(2) * aa / (s * s); }
+        const T is2 = mrcp(s * s);
+        if (aa < ab) { dpa = T(2) * ab * is2; dpb = -T(2) * aa * is2; }
+        else { dpa = -T(2) * ab * is2; dpb = T(2) * aa * is2; }
         dpa = (a < T(0)) ? -dpa : dpa;
         dpb = (b < T(0)) ? -dpb : dpb;
       } else {
         T s = a * a + b * b;
         // phi = 2 a b / (a^2 + b^2)
-        dpa = T(2) * b * (b * b - a * a) / (s * s);
-        dpb = T(2) * a * (a * a - b * b) / (s * s);
+        const T is2 = mrcp(s * s);
+        dpa = T(2) * b * (b * b - a * a) * is2;
+        dpb = T(2) * a * (a * a - b * b) * is2;
       }
       T ab_ = phib * dpa, bb_ = phib * dpb;
       // a = Wc - Wm, b = Wp - Wc

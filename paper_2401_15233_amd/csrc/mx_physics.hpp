@@ -47,7 +47,48 @@ template <class T> MX_HD T tmax(T a, T b) { return a > b ? a : b; }
 template <class T> MX_HD T tmin(T a, T b) { return a < b ? a : b; }
 template <class T> MX_HD T tabs(T a) { return a < T(0) ? -a : a; }
 
+// FP64 square root, reciprocal and quotient.  On the device: the hardware reciprocal /
+// reciprocal-square-root seed (single-precision accurate) refined by Newton-Raphson -- two
+// steps of r <- r + r (1 - b r) for 1/b, then one residual correction of the quotient; for the
+// square root two steps of the coupled iteration on g ~ sqrt(a), h ~ 1/(2 sqrt(a)) with
+// r = 1/2 - g h, then one residual correction -- about 1 ulp, in fewer instructions than the
+// correctly rounded sequences.  The arguments of the step (densities, pressures, determinants,
+// positive sums) are positive and far from the exponent range's ends; sqrt(0) = 0 is kept, and
+// a negative, zero-divisor or non-finite argument still gives a non-finite result, which the
+// step's state check reports.  On the host: the IEEE operations.
+#if defined(__HIP_DEVICE_COMPILE__)
+MX_HD double msqrt(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  const double d = __builtin_fma(-g, g, a);
+  const double s = __builtin_fma(d, h, g);
+  return a == 0.0 ? a : s;
+}
+MX_HD double mrcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+MX_HD double mdiv(double a, double b) {
+  const double r = mrcp(b);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+#else
 MX_HD double msqrt(double a) { return sqrt(a); }
+MX_HD double mrcp(double b) { return 1.0 / b; }
+MX_HD double mdiv(double a, double b) { return a / b; }
+#endif
+template <class T> MX_HD T mrcp(T b) { return T(1) / b; }
+template <class T> MX_HD T mdiv(T a, T b) { return a / b; }
 MX_HD double mexp(double a) { return exp(a); }
 MX_HD double mlog(double a) { return log(a); }
 // single precision: the hardware square root / exponential / logarithm (about 1 ulp)
@@ -100,7 +141,7 @@ template <class T> MX_HD bool spd_ok(T rho, const T* P) {
 // positive root of the mapping quadratic, cancellation-free for A < 0
 template <class T> MX_HD T sigma_root(T A, T X, T num_small, T denom_big) {
   T sX = msqrt(X);
-  return (A >= T(0)) ? (A + sX) / denom_big : num_small / (sX - A);
+  return (A >= T(0)) ? mdiv(A + sX, denom_big) : mdiv(num_small, sX - A);
 }
 
 // zeta + sqrt(max(0, zeta^2 + rest)), cancellation-free for zeta < 0
@@ -108,7 +149,7 @@ template <class T> MX_HD T hyperbola(T zeta, T rest) {
   T X = zeta * zeta + rest;
   if (!(X > T(0))) return zeta;
   T sX = msqrt(X);
-  return (zeta >= T(0)) ? zeta + sX : rest / (sX - zeta);
+  return (zeta >= T(0)) ? zeta + sX : mdiv(rest, sX - zeta);
 }
 
 // Baradaran's B, Y, E, C at sigma_w and the normal pressure P*_dd
@@ -130,7 +171,7 @@ struct Sys14 {
 
   template <class T> MX_HD static void cons_to_prim(const T* U, T* W) {
     T rho = U[0];
-    T ir = T(1) / rho;
+    T ir = mrcp(rho);
     T u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
     T P[6];
 #pragma unroll
@@ -185,7 +226,7 @@ struct Sys14 {
   template <class T> MX_HD static void scales(const T* W, T* sc) {
     T rho = tabs(W[0]);
     T p = tabs(W[4] + W[7] + W[9]) * T(1.0 / 3.0);
-    T c = msqrt(p / rho);
+    T c = msqrt(mdiv(p, rho));
     T c3 = rho * c * c * c;
     sc[0] = rho;
     sc[1] = sc[2] = sc[3] = c;
@@ -210,8 +251,8 @@ struct Sys14 {
   template <class T> MX_HD static void core(const T* W, T sigma_lim, Core<T>& k) {
     k.rho = W[0];
     T p = (W[4] + W[7] + W[9]) * T(1.0 / 3.0);
-    T irho = T(1) / k.rho;
-    T ip = T(1) / p;
+    T irho = mrcp(k.rho);
+    T ip = mrcp(p);
     k.c = msqrt(p * irho);
     T ic = msqrt(k.rho * ip);          // 1 / c
 #pragma unroll
@@ -225,7 +266,7 @@ struct Sys14 {
     k.t2 = k.P2[0] + k.P2[3] + k.P2[5];
     T C[6];
     T det = symadj(k.Ph, C);
-    T idet = T(1) / det;
+    T idet = mrcp(det);
     T y[3];
     symv(C, k.qh, y);
 #pragma unroll
@@ -243,7 +284,7 @@ struct Sys14 {
   // 1/sigma, so A and the traces it needs are formed in FP64; the rest in FP32.
   MX_HD static void core_mixed(const double* W, float sigma_lim, Core<float>& k) {
     double p = (W[4] + W[7] + W[9]) * (1.0 / 3.0);
-    double ip = 1.0 / p;
+    double ip = mrcp(p);
     double Ph[6], P2[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) Ph[m] = W[4 + m] * ip;
@@ -289,7 +330,7 @@ struct Sys14 {
     T detc = symadj(Cm, Ca);
     T y[3];
     symv(Ca, k.qh, y);
-    T idc = T(1) / detc;
+    T idc = mrcp(detc);
     T w[3] = {y[0] * idc, y[1] * idc, y[2] * idc};
     T P2z[3];
     symv(k.P2, k.z, P2z);
@@ -306,7 +347,7 @@ struct Sys14 {
         Qd[sidx(i, j)] = T(2) * (w[i] * k.P2[sidx(j, d)] + w[j] * k.P2[sidx(i, d)] +
                                  w[d] * k.P2[sidx(i, j)]) * s3;
     // R_id(kk)
-    T isb = T(1) / k.sb;
+    T isb = mrcp(k.sb);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T Qz = T(2) * (w[i] * P2z[d] + w[d] * P2z[i] + wz * k.P2[sidx(i, d)]);
@@ -382,7 +423,7 @@ struct Sys14 {
       b = T(0.9) * Pdd * mexp(T(-0.5) * mexp(T(1.4) * lP));
     }
     BYEC<T> g = byec(sw, Pdd);
-    T pref = (a * sw + b) / (T(2) * sw);
+    T pref = mdiv(a * sw + b, T(2) * sw);
     T base = T(4) * sw * sw * g.Y + qt * qt * T(0.1);
     T zmax = qd + qt * alpha;
     T zmin = -qd + qt * alpha;
@@ -460,7 +501,7 @@ struct Sys14 {
         C[4 + sidx(i, j)] = -(P[sidx(i, j)] - (i == j ? p : T(0))) * inv_tau;
 #pragma unroll
     for (int i = 0; i < 3; ++i) C[10 + i] = -(T(2) * Pu[i] + q[i] - T(2) * u[i] * p) * inv_tau;
-    C[13] = -((T(4) * uPu + T(4) * uq + W[13]) - (T(4) * uu * p + T(15) * p * p / rho)) * inv_tau;
+    C[13] = -((T(4) * uPu + T(4) * uq + W[13]) - (T(4) * uu * p + mdiv(T(15) * p * p, rho))) * inv_tau;
   }
 };
 
@@ -470,7 +511,7 @@ struct Sys5 {
 
   template <class T> MX_HD static void cons_to_prim(const T* U, T* W) {
     T rho = U[0];
-    T u = U[1] / rho;
+    T u = mdiv(U[1], rho);
     T P = U[2] - rho * u * u;
     T q = U[3] - rho * u * u * u - T(3) * u * P;
     T r = U[4] - rho * u * u * u * u - T(6) * u * u * P - T(4) * u * q;
@@ -492,7 +533,7 @@ struct Sys5 {
   template <class T> MX_HD static void scales(const T* W, T* sc) {
     T rho = tabs(W[0]);
     T p = tabs(W[2]);
-    T c = msqrt(p / rho);
+    T c = msqrt(mdiv(p, rho));
     sc[0] = rho; sc[1] = c; sc[2] = p; sc[3] = rho * c * c * c; sc[4] = sc[3] * c;
   }
 
@@ -502,8 +543,8 @@ struct Sys5 {
 
   template <class T> MX_HD static void core(const T* W, T sigma_lim, Core<T>& k) {
     k.rho = W[0];
-    T irho = T(1) / k.rho;
-    T ip = T(1) / W[2];
+    T irho = mrcp(k.rho);
+    T ip = mrcp(W[2]);
     k.c = msqrt(W[2] * irho);
     T ic = msqrt(k.rho * ip);
     T is3 = irho * (ic * ic * ic);
@@ -517,7 +558,7 @@ struct Sys5 {
   }
 
   MX_HD static void core_mixed(const double* W, float sigma_lim, Core<float>& k) {
-    double ip = 1.0 / W[2];
+    double ip = mrcp(W[2]);
     double A = 3.0 - W[4] * W[0] * ip * ip;
     k.rho = (float)W[0];
     float irho = 1.0f / k.rho;
@@ -533,7 +574,7 @@ struct Sys5 {
   }
 
   template <class T> MX_HD static T closing_s(const Core<T>& k) {
-    T ss = k.qh * k.qh * k.qh / (k.sb * k.sb) + (T(10) - T(8) * msqrt(k.sb)) * k.qh;
+    T ss = mdiv(k.qh * k.qh * k.qh, k.sb * k.sb) + (T(10) - T(8) * msqrt(k.sb)) * k.qh;
     T c2 = k.c * k.c;
     return ss * k.rho * (c2 * c2 * k.c);
   }
@@ -552,7 +593,7 @@ struct Sys5 {
     T sw = tmin(k.sb, T(1));
     BYEC<T> g = byec(sw, T(1));
     T base = T(4) * sw * sw * g.Y;
-    T i2s = T(1) / (T(2) * sw);
+    T i2s = mrcp(T(2) * sw);
     T Lmax = hyperbola(k.qh, T(-0.8) * k.qh * sw * g.C + base) * i2s + g.E;
     T Lmin = hyperbola(-k.qh, T(0.8) * k.qh * sw * g.C + base) * i2s + g.E;
     lmax = u + kws * Lmax * k.c;
@@ -592,7 +633,7 @@ struct Sys5 {
     T rho = W[0], u = W[1], P = W[2], q = W[3], r = W[4];
     C[0] = C[1] = C[2] = T(0);
     C[3] = -q * inv_tau;
-    C[4] = -(T(4) * u * q + r - T(3) * P * P / rho) * inv_tau;
+    C[4] = -(T(4) * u * q + r - mdiv(T(3) * P * P, rho)) * inv_tau;
   }
 };
 

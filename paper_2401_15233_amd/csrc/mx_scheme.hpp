@@ -34,7 +34,7 @@ MX_HD T limiter_factor(const T* Wm, const T* Wc, const T* Wp, int kind) {
     else { fn = T(2) * a * b; fd = a * a + b * b; }
     if (fn * den < num * fd) { num = fn; den = fd; }
   }
-  return (den == T(1)) ? num : num / den;
+  return (den == T(1)) ? num : mdiv(num, den);
 }
 
 template <class SYS, class T>
@@ -64,7 +64,7 @@ MX_HD void face_flux(const T* WL, const T* WR, T sigma_lim, T kws, int flux_kind
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fh[v] = FR[v];
     } else {
-      T inv = T(1) / (SR - SL);
+      T inv = mrcp(SR - SL);
       T SLR = SL * SR;
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fh[v] = (SR * FL[v] - SL * FR[v] + SLR * (UR[v] - UL[v])) * inv;
