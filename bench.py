@@ -210,8 +210,9 @@ def main():
                     help='only run a plain 2 GiB device copy (HBM counter calibration)')
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
-        print('bench.py runs on exactly one GPU: the solver has no multi-GPU path (the '
-              'halo-exchange design is described in DESIGN.md); use --gpus 1', file=sys.stderr)
+        print('bench.py runs on exactly one GPU: the solver has no multi-GPU path (a slab '
+              'decomposition with ghost-row exchange is the intended design); use --gpus 1',
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

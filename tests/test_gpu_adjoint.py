@@ -232,6 +232,45 @@ def test_adjoint_argument_and_state_errors(gpu_lib):
     m.close()
 
 
+def test_adjoint_of_an_empty_tape_is_the_identity(gpu_lib):
+    kw = dict(JETS, nx=20, ny=16)
+    U0 = mo.prim_to_cons14(I.crossed_jets_developed(20, 16, seed=15))
+    w = random_weights(20, 16, 1 / 20, 1 / 16, seed=16)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(np.ascontiguousarray(U0), repr='conserved')
+    s.record(3, 5)
+    gU0, g = s.adjoint(w)
+    assert g == [0.0, 0.0, 0.0]
+    assert np.array_equal(gU0.cpu().numpy(), w)
+    s.close()
+
+
+def test_adjoint_ignores_steps_after_t_end(gpu_lib):
+    """Steps requested after t_end are recorded with dt = 0 and reverse to the identity: the
+    gradients equal those of the run that stops exactly at t_end."""
+    kw = dict(JETS, nx=24, ny=20)
+    U0 = mo.prim_to_cons14(I.crossed_jets_developed(24, 20, seed=17))
+    w = random_weights(24, 20, 1 / 24, 1 / 20, seed=18)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(np.ascontiguousarray(U0), repr='conserved')
+    dt = s.step(1, tau_ref=TAU_JET)['dt_last']
+    t_end = 3.5 * dt                       # the fourth step is clipped to half a step
+    res = []
+    for n in (4, 9):
+        s.record(0, 0)
+        s.init_state(np.ascontiguousarray(U0), repr='conserved')
+        s.record(2, n)
+        info = s.step(n, tau_ref=TAU_JET, t_end=t_end)
+        assert info['steps'] == 4 and abs(info['t'] - t_end) < 1e-15
+        dts = s.tape()
+        assert len(dts) == n and np.all(dts[4:] == 0.0)
+        gU0, g = s.adjoint(w)
+        res.append((gU0.cpu().numpy(), g))
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][0], res[1][0])
+    s.close()
+
+
 def test_autograd_function_matches_direct_adjoint(gpu_lib):
     import torch
     from paper_2401_15233_amd.autograd import MaxEntSteps
