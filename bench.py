@@ -234,11 +234,11 @@ def main():
     stream = torch.cuda.current_stream()
     W0 = inputs.crossed_jets_initial(n, n)
 
-    def timed(precision):
+    def timed(precision, init=None):
         kw = jets_kwargs(n)
         kw['precision'] = precision
         s = solver.MaxEntSolver(stream=stream, **kw)
-        s.init_state(W0)
+        s.init_state(W0 if init is None else init)
         if a.warmup:
             s.step(a.warmup, tau_ref=tau)
         s.set_profiling(True)
@@ -295,6 +295,14 @@ def main():
                      'hbm_achieved_gbs': hbm_achieved,
                      'hbm_frac': hbm_achieved / HBM_PEAK_GBS},
     }
+    def fp64_sensitivity():
+        rng = np.random.default_rng(0)
+        Wp = W0 * (1.0 + rng.choice([-1.0, 1.0], W0.shape) * 2.0 ** -24)
+        U_p = timed('fp64', init=Wp)[4]
+        dd = (U_p - U_head).abs().reshape(14, -1).sum(1)
+        rr = U_head.abs().reshape(14, -1).sum(1).clamp_min(1e-300)
+        return [float(x) for x in (dd / rr).cpu()]
+
     if a.precision == 'both':
         ms_m, stage_ms_m, launches_m, info_m, U_m = timed('mixed')
         d = (U_m - U_head).abs().reshape(14, -1).sum(1)
@@ -307,6 +315,10 @@ def main():
             'alu_tflops_algorithmic': flops_per_launch / (avg_m / 1e3) / 1e12,
             'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms_m / 1e3) / 1e9,
             'l1_rel_deviation_from_fp64_per_moment': [float(x) for x in (d / ref).cpu()],
+            # the FP64 run's own L1 change when its initial state carries one random FP32
+            # rounding (+-2^-24 relative): how far this flow amplifies single-precision
+            # rounding over the same steps
+            'fp64_l1_change_under_fp32_input_rounding_per_moment': fp64_sensitivity(),
             'fp64_reevaluated_face_state_fraction':
                 info_m['n_fp64_states'] / max(info_m['n_face_states'], 1),
         }
