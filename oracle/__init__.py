@@ -20,7 +20,7 @@ Modules
   wavespeeds  -- Baradaran 5-moment and the paper's approximate 14-moment wave speeds
   fluxes      -- physical fluxes, BGK sources, local collision time, HLL and Rusanov
   scheme      -- MUSCL with the common limiter, ghost cells, residual, CFL dt, integrators
-  problems    -- Sod and crossed-jet set-ups expressed through the oracle's own routines
+  eigen       -- flux-Jacobian eigenvalues of the closed systems (diagnostic of the wave-speed fits)
 """
 
-from . import moments, closure, wavespeeds, fluxes, scheme  # noqa: F401
+from . import moments, closure, wavespeeds, fluxes, scheme, eigen  # noqa: F401
