@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MAXENT_ABI_VERSION 1
+#define MAXENT_ABI_VERSION 2
 
 typedef struct maxent_solver maxent_solver;
 
@@ -59,10 +59,14 @@ enum { MAXENT_PRIMITIVE = 0, MAXENT_CONSERVED = 1, MAXENT_SIGMA = 2 };
  *   dim, nx, ny   1 or 2; ny = 1 when dim = 1.  nx, ny >= 4.
  *   x0..y1        domain; uniform cells dx = (x1-x0)/nx, dy = (y1-y0)/ny.
  *   bc[4]         XLO, XHI, YLO, YHI boundary kinds (MAXENT_BC_*).  PERIODIC must be set on
- *                 both sides of an axis.  JET is accepted on XLO only (Section 6): ghost
- *                 cells of rows whose centre y lies in [yc - w/2, yc + w/2] of a jet hold
- *                 the jet Maxwellian, other rows are transmissive.
- *   jets          up to 4 (centre y, width, angle in degrees from +x toward +y).
+ *                 both sides of an axis.  JET (2D, 14 moments; Section 6): on a JET side,
+ *                 the ghost cells of the boundary rows (x sides) or columns (y sides) whose
+ *                 centre lies in [c - w/2, c + w/2] of a jet on that side hold the jet
+ *                 Maxwellian; the others are transmissive.  Every JET side needs a jet.
+ *   jets          up to 4: centre c along its wall (y on the x sides, x on the y sides),
+ *                 width w, angle in degrees from +x toward +y, and jet_wall[k] (0 XLO,
+ *                 1 XHI, 2 YLO, 3 YHI; that side must be JET).  The paper's crossed jets are
+ *                 a jet on XLO at angle 0 and one on YLO at angle 90, both of width L/7.
  *   jet_mach, jet_rho, jet_T   the jet Maxwellian: |u| = M sqrt(5/3 T), P = rho T I,
  *                 q = 0, R = 15 p^2 / rho.
  *   tau_mode      LOCAL: tau = tau_ref (rho_ref/rho) sqrt(T_ref/T) at each cell centre, the
@@ -78,6 +82,7 @@ typedef struct {
   double jet_mach, jet_rho, jet_T;
   int tau_mode;
   double rho_ref, T_ref;
+  int jet_wall[4];
 } maxent_problem;
 
 /* Numerics.
@@ -97,7 +102,14 @@ typedef struct {
  *   sigma_lim     lower bound of the parabolic-mapping parameter (Appendix A), e.g. 1e-4.
  *   k_ws          wave-speed inflation factor k >= 1 (Section 5.1).
  *   positivity_fallback  1: a cell whose reconstructed face states along a direction have
- *                 rho <= 0 or a non-positive-definite P is reconstructed at first order. */
+ *                 rho <= 0 or a non-positive-definite P is reconstructed at first order.
+ *   source_implicit  0: explicit BGK source.  1 (FE integrator only): point-implicit BGK
+ *                 relaxation, the remedy the paper names for stiff collisions (Section 4.3,
+ *                 Kn below about 1e-4): the transported state U_t = U + dt (fluxes) relaxes
+ *                 by backward Euler, U_new = (U_t + h U_eq) / (1 + h), h = dt / tau, where
+ *                 U_eq is the local Maxwellian of U_t and tau is evaluated from U_t (the
+ *                 source keeps rho, rho u and the energy, so this is exact backward Euler for
+ *                 the source).  Not available with the adjoint. */
 typedef struct {
   int precision;
   int order;
@@ -106,6 +118,7 @@ typedef struct {
   int integrator;
   double cfl, sigma_lim, k_ws;
   int positivity_fallback;
+  int source_implicit;
 } maxent_numerics;
 
 /* Per-call report of maxent_step. */
@@ -194,6 +207,10 @@ int maxent_create_batch(const maxent_problem* common, const maxent_numerics* num
                         maxent_solver** out);
 
 /* Advance every instance until it reaches its t_end, or at most about max_steps steps.
+ * The instances form a queue ordered by estimated work (cells x steps to t_end from the
+ * CFL rate of the state given to init_state, largest first; ties by index).  Each step
+ * compacts the instances that still advance, in queue order, into a list of tiles that the
+ * stage launches split evenly over their workgroups, so finished instances cost nothing.
  * Steps are replayed in chunks of `chunk` steps captured once as a HIP graph (on an internal
  * stream of default priority, ordered after earlier work on the solver's stream); after each
  * chunk one word is read to see whether any instance is still active.  per_inst may be NULL
@@ -201,16 +218,18 @@ int maxent_create_batch(const maxent_problem* common, const maxent_numerics* num
 int maxent_step_batch(maxent_solver* s, int max_steps, int chunk, maxent_batch_info* info,
                       maxent_instance_info* per_inst);
 
-/* Launch shape of the batched stage kernels: threads per workgroup (64, 128 or 256; a tile
- * holds threads - 1 cells) and persistent workgroups per compute unit (1..32). */
-int maxent_set_batch_launch(maxent_solver* s, int threads, int wg_per_cu);
-int maxent_get_batch_launch(maxent_solver* s, int* threads, int* wg_per_cu);
+/* Launch shape of the batched stage kernels: threads per workgroup (64, 128 or 256), cells
+ * per thread (1, 2 or 4, with threads x cells per thread <= 256; a tile holds
+ * threads x cells per thread - 4 cells, so that the tile and its two-cell halos fill whole
+ * rounds over the threads) and workgroups per compute unit (1..32).  INVAL for other values. */
+int maxent_set_batch_launch(maxent_solver* s, int threads, int cells_per_thread, int wg_per_cu);
+int maxent_get_batch_launch(maxent_solver* s, int* threads, int* cells_per_thread, int* wg_per_cu);
 
-/* Autotuner: time trial_steps steps of each launch shape (threads 64/128/256 x workgroups
- * per CU 2/4/8/16) from the current state, restoring the state after every trial, and keep
- * the fastest.  Outputs may be NULL. */
-int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* wg_per_cu,
-                          double* best_cell_updates_per_s);
+/* Autotuner: time trial_steps steps of each launch shape (threads x cells per thread in
+ * 64x1, 64x2, 64x4, 128x1, 128x2, 256x1, times workgroups per CU 2/4/8/16) from the current
+ * state, restoring the state after every trial, and keep the fastest.  Outputs may be NULL. */
+int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* cells_per_thread,
+                          int* wg_per_cu, double* best_cell_updates_per_s);
 
 /* ------------------------------------------------------------------ discrete adjoint
  * Reverse-mode derivatives of a scalar J(U_final) through the recorded steps: the hand-written

@@ -31,8 +31,11 @@ Readings (silent points; each also listed in the design notes)
     T = p/rho; tau_ref <= 0 switches the source off (collisionless).
   * ghost cells are filled in primitive variables: transmissive copies the edge cell,
     periodic wraps, reflective mirrors and negates the components odd in the normal
-    direction, jet inflow writes the jet Maxwellian into the ghost cells of the rows whose
-    centre lies in a jet and is transmissive elsewhere.
+    direction, jet inflow writes the jet Maxwellian into the ghost cells of the boundary
+    rows (x walls) or columns (y walls) whose centre lies in a jet on that wall and is
+    transmissive elsewhere (Section 6: jets centred on the walls, L/7 wide).
+  * point-implicit source (forward Euler only; Section 4.3 names it for stiff collisions):
+    transport by forward Euler, then the BGK source alone by backward Euler.
 """
 from dataclasses import dataclass, field
 import math
@@ -57,7 +60,9 @@ class Setup:
     y0: float = 0.0
     y1: float = 1.0
     bc: tuple = ('transmissive',) * 4  # XLO, XHI, YLO, YHI
-    jets: list = field(default_factory=list)   # [(y_centre, width, angle_deg), ...]
+    # [(centre along the wall, width, angle_deg[, wall]), ...]; wall 0 x-low (default),
+    # 1 x-high, 2 y-low, 3 y-high
+    jets: list = field(default_factory=list)
     jet_mach: float = 3.0
     jet_rho: float = 1.0
     jet_T: float = 1.0
@@ -72,6 +77,7 @@ class Setup:
     sigma_lim: float = 1e-4
     k_ws: float = 1.0
     positivity_fallback: bool = True
+    source_implicit: bool = False     # forward Euler with a backward-Euler BGK source
 
     @property
     def nv(self):
@@ -120,8 +126,9 @@ def _odd_components(system, d):
     return uo + Po + qo
 
 
-def pad_axis(W, g, axis, lo, hi, s, y_centres=None):
-    """Add g ghost layers along array axis `axis` (component axis is 0)."""
+def pad_axis(W, g, axis, lo, hi, s, wall_centres=None):
+    """Add g ghost layers along array axis `axis` (component axis is 0).  wall_centres: the
+    coordinates, along the wall, of the cells of the other array axis (for jet inflow)."""
     n = W.shape[axis]
     d = 0 if axis == W.ndim - 1 else 1          # physical direction: last axis is x
     idx = np.arange(-g, n + g)
@@ -147,13 +154,18 @@ def pad_axis(W, g, axis, lo, hi, s, y_centres=None):
                 gh[c] = -gh[c]
             out[tuple(sl)] = gh
         elif kind == 'jet':
-            if side != 'lo' or d != 0:
-                raise ValueError('jet inflow is a left (x-low) boundary')
-            gh = out[tuple(sl)].copy()                  # (nv, ny, g)
-            for (yc, w, ang) in s.jets:
+            wall = 2 * d + (0 if side == 'lo' else 1)
+            gh = out[tuple(sl)].copy()       # (nv, ny, g) on the x walls, (nv, g, nx) on y
+            for jet in s.jets:
+                centre, w, ang = jet[:3]
+                if (jet[3] if len(jet) > 3 else 0) != wall:
+                    continue
                 Wj = jet_prim(s, ang)
-                rows = (y_centres >= yc - 0.5 * w) & (y_centres <= yc + 0.5 * w)
-                gh[:, rows, :] = Wj[:, None, None]
+                band = (wall_centres >= centre - 0.5 * w) & (wall_centres <= centre + 0.5 * w)
+                if d == 0:
+                    gh[:, band, :] = Wj[:, None, None]
+                else:
+                    gh[:, :, band] = Wj[:, None, None]
             out[tuple(sl)] = gh
         else:
             raise ValueError(kind)
@@ -166,8 +178,9 @@ def ghosted_prims(U, s, g):
     if s.dim == 1:
         return pad_axis(W, g, 1, s.bc[0], s.bc[1], s)
     yc = s.y0 + (np.arange(s.ny) + 0.5) * s.dy
-    Wx = pad_axis(W, g, 2, s.bc[0], s.bc[1], s, y_centres=yc)
-    return pad_axis(Wx, g, 1, s.bc[2], s.bc[3], s)
+    xc = s.x0 + (np.arange(-g, s.nx + g) + 0.5) * s.dx     # columns of the x-padded field
+    Wx = pad_axis(W, g, 2, s.bc[0], s.bc[1], s, wall_centres=yc)
+    return pad_axis(Wx, g, 1, s.bc[2], s.bc[3], s, wall_centres=xc)
 
 
 # ----------------------------------------------------------------------------- MUSCL
@@ -343,8 +356,35 @@ def check_state(U, s, step):
         raise OracleFailure(f'unrealizable state (rho <= 0 or P not SPD) after step {step}')
 
 
+def relax_backward_euler(Ut, h_dt, s, tau_ref):
+    """Backward-Euler step of the BGK source alone, U = Ut + h_dt C(U).  The source relaxes
+    the non-conserved moments towards the local Maxwellian and keeps rho, rho u and the
+    energy (Sections 2.3-2.4), so the Maxwellian U_eq and the collision time of U are those
+    of Ut, and C(U) = (U_eq - U) / tau makes the implicit equation linear:
+    U = (Ut + (h_dt / tau) U_eq) / (1 + h_dt / tau)."""
+    if not (tau_ref > 0.0) or math.isinf(tau_ref):
+        return Ut
+    W = cons_to_prim(Ut, s)
+    rho = W[0]
+    if s.system == 5:
+        T = W[2] / rho
+        Weq = mo.maxwellian_prim5(rho, W[1], W[2])
+    else:
+        p = mo.pressure14(W)
+        T = p / rho
+        Weq = mo.maxwellian_prim14(rho, np.moveaxis(W[1:4], 0, -1), p)
+    tau = tau_local(rho, T, tau_ref, s.rho_ref, s.T_ref) if s.tau_mode == 'local' \
+        else tau_ref + np.zeros_like(rho)
+    h = h_dt / tau
+    return (Ut + h * prim_to_cons(Weq, s)) / (1.0 + h)
+
+
 def step(U, dt, s, tau_ref, stats=None):
     """One full time step with the configured integrator (ghosts refilled per stage)."""
+    if s.source_implicit:
+        if s.integrator != 'fe':
+            raise ValueError('the implicit source is defined for forward Euler')
+        return relax_backward_euler(U + dt * residual(U, s, 0.0, stats), dt, s, tau_ref)
     L0 = residual(U, s, tau_ref, stats)
     if s.integrator == 'fe':
         return U + dt * L0

@@ -317,8 +317,21 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
     const long long e = (long long)ej * a.epitch + (i + 2);
 #pragma unroll
     for (int v = 0; v < 14; ++v) Wb[v] = a.wb[v * a.eplane + e];
+    // a ghost cell holding a jet state: its adjoint goes to the jet parameters
+    auto fold_jet = [&](int jet, long long eg) {
+      double sn, cs;
+      sincospi(p.jet_ang[jet] / 180.0, &sn, &cs);
+      const double T = p.jet_T;
+      const double c0 = sqrt(5.0 / 3.0 * T);
+      double G[14];
+#pragma unroll
+      for (int v = 0; v < 14; ++v) G[v] = a.wb[v * a.eplane + eg];
+      gM += (G[1] * cs + G[2] * sn) * c0;
+      gR += G[0] + T * (G[4] + G[7] + G[9]) + 15.0 * T * T * G[13];
+    };
     // ghost cells along x in this row that copy cell (i, j)
-    const int jet = (p.bc[0] == 3) ? jet_of_row(p, j) : -1;
+    const int jet_lo = (p.n_jets > 0 && p.bc[0] == 3) ? jet_on_wall(p, 0, j) : -1;
+    const int jet_hi = (p.n_jets > 0 && p.bc[1] == 3) ? jet_on_wall(p, 1, j) : -1;
     const int gx[4] = {-2, -1, p.nx, p.nx + 1};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -327,17 +340,9 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
       const int si = map_axis(g, p.nx, p.bc[0], p.bc[1], rx);
       if (si != i) continue;
       const long long eg = ext(g, j);
-      if (g < 0 && jet >= 0) {
-        // the ghost holds the jet state: its adjoint goes to the jet parameters
-        double sn, cs;
-        sincospi(p.jet_ang[jet] / 180.0, &sn, &cs);
-        const double T = p.jet_T;
-        const double c0 = sqrt(5.0 / 3.0 * T);
-        double G[14];
-#pragma unroll
-        for (int v = 0; v < 14; ++v) G[v] = a.wb[v * a.eplane + eg];
-        gM += (G[1] * cs + G[2] * sn) * c0;
-        gR += G[0] + T * (G[4] + G[7] + G[9]) + 15.0 * T * T * G[13];
+      const int jet = g < 0 ? jet_lo : jet_hi;
+      if (jet >= 0) {
+        fold_jet(jet, eg);
         continue;
       }
 #pragma unroll
@@ -347,6 +352,8 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
       }
     }
     if constexpr (DIM == 2) {
+      const int jet_blo = (p.n_jets > 0 && p.bc[2] == 3) ? jet_on_wall(p, 2, i) : -1;
+      const int jet_bhi = (p.n_jets > 0 && p.bc[3] == 3) ? jet_on_wall(p, 3, i) : -1;
       const int gy[4] = {-2, -1, p.ny, p.ny + 1};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -355,6 +362,11 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
         const int sj = map_axis(g, p.ny, p.bc[2], p.bc[3], ry);
         if (sj != j) continue;
         const long long eg = ext(i, g);
+        const int jet = g < 0 ? jet_blo : jet_bhi;
+        if (jet >= 0) {
+          fold_jet(jet, eg);
+          continue;
+        }
 #pragma unroll
         for (int v = 0; v < 14; ++v) {
           double gv = a.wb[v * a.eplane + eg];

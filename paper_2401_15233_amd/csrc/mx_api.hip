@@ -14,7 +14,8 @@
 
 using mx::DevCtrl;
 
-// batched 1D tubes: per-instance records, static tile lists per tile width, graph of a chunk
+// batched 1D tubes: per-instance records, the work-ordered instance queue, the per-step work
+// list, graph of a chunk
 struct BatchState {
   int n_inst = 0;
   long long total = 0;
@@ -23,10 +24,13 @@ struct BatchState {
   mx::BatchInst* h_inst = nullptr;       // pinned read-back
   mx::BatchCtrl* d_ctrl = nullptr;
   mx::BatchCtrl* h_ctrl = nullptr;       // pinned read-back
-  int2* d_tiles[3] = {nullptr, nullptr, nullptr};   // tile widths 63, 127, 255
-  int n_tiles[3] = {0, 0, 0};
+  std::vector<int> order;                // instance queue, largest estimated work first
+  int* d_order = nullptr;
+  int* d_act_inst = nullptr;             // per step: instances that advance, in queue order
+  int* d_act_tile0 = nullptr;            // per step: their first tile in the work list (n_inst + 1)
   int* d_cell_inst = nullptr;
-  int nt = 64;                           // threads per workgroup = tile width + 1
+  int nt = 64;                           // threads per workgroup
+  int cpt = 1;                           // cells per thread: tiles of tile_1d(nt * cpt) cells
   int wg_per_cu = 4;
   int n_cu = 256;
   hipStream_t gstream = nullptr;         // capture stream (a captured graph cannot use the null stream)
@@ -120,14 +124,23 @@ static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
     return "periodic x needs both x sides periodic";
   if (p.dim == 2 && ((p.bc[2] == MAXENT_BC_PERIODIC) != (p.bc[3] == MAXENT_BC_PERIODIC)))
     return "periodic y needs both y sides periodic";
-  for (int k = 1; k < nb; ++k)
-    if (p.bc[k] == MAXENT_BC_JET) return "jet inflow is only allowed on the x-low side";
-  if (p.bc[0] == MAXENT_BC_JET) {
+  bool any_jet = false;
+  for (int k = 0; k < nb; ++k) any_jet = any_jet || p.bc[k] == MAXENT_BC_JET;
+  if (any_jet) {
     if (p.system != 14 || p.dim != 2) return "jet inflow needs the 2D 14-moment system";
     if (p.n_jets < 1 || p.n_jets > 4) return "n_jets must be 1..4";
     if (!(p.jet_rho > 0) || !(p.jet_T > 0) || !(p.jet_mach >= 0)) return "bad jet state";
-    for (int k = 0; k < p.n_jets; ++k)
+    for (int k = 0; k < p.n_jets; ++k) {
       if (!(p.jet_width[k] > 0)) return "jet width must be positive";
+      if (p.jet_wall[k] < 0 || p.jet_wall[k] > 3) return "jet_wall must be 0..3";
+      if (p.bc[p.jet_wall[k]] != MAXENT_BC_JET) return "a jet's wall must have the JET boundary kind";
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (p.bc[w] != MAXENT_BC_JET) continue;
+      bool has = false;
+      for (int k = 0; k < p.n_jets; ++k) has = has || p.jet_wall[k] == w;
+      if (!has) return "a JET side needs at least one jet on it";
+    }
   }
   if (p.tau_mode != MAXENT_TAU_LOCAL && p.tau_mode != MAXENT_TAU_CONST) return "bad tau_mode";
   if (p.tau_mode == MAXENT_TAU_LOCAL && !(p.rho_ref > 0 && p.T_ref > 0)) return "bad rho_ref/T_ref";
@@ -139,6 +152,8 @@ static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
   if (!(n.cfl > 0 && n.cfl <= 1)) return "cfl must be in (0, 1]";
   if (!(n.sigma_lim > 0 && n.sigma_lim < 1)) return "sigma_lim must be in (0, 1)";
   if (!(n.k_ws >= 1)) return "k_ws must be >= 1";
+  if (n.source_implicit != 0 && n.source_implicit != 1) return "source_implicit must be 0 or 1";
+  if (n.source_implicit && n.integrator != MAXENT_FE) return "the implicit source needs the FE integrator";
   return "";
 }
 
@@ -185,8 +200,9 @@ extern "C" void maxent_destroy(maxent_solver* s) {
     if (b->h_inst) (void)hipHostFree(b->h_inst);
     if (b->d_ctrl) (void)hipFree(b->d_ctrl);
     if (b->h_ctrl) (void)hipHostFree(b->h_ctrl);
-    for (int k = 0; k < 3; ++k)
-      if (b->d_tiles[k]) (void)hipFree(b->d_tiles[k]);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_act_inst) (void)hipFree(b->d_act_inst);
+    if (b->d_act_tile0) (void)hipFree(b->d_act_tile0);
     if (b->d_cell_inst) (void)hipFree(b->d_cell_inst);
     delete b;
   }
@@ -240,17 +256,21 @@ static mx::StageParams stage_params(maxent_solver* s, double tau_ref) {
   p.inv_dx = 1.0 / p.dx;
   p.inv_dy = 1.0 / p.dy;
   for (int k = 0; k < 4; ++k) p.bc[k] = q.bc[k];
-  p.n_jets = q.bc[0] == MAXENT_BC_JET ? q.n_jets : 0;
+  bool any_jet = false;
+  for (int k = 0; k < 4; ++k) any_jet = any_jet || q.bc[k] == MAXENT_BC_JET;
+  p.n_jets = any_jet ? q.n_jets : 0;
   for (int k = 0; k < 4; ++k) {
     p.jet_yc[k] = q.jet_yc[k]; p.jet_w[k] = q.jet_width[k]; p.jet_ang[k] = q.jet_angle_deg[k];
+    p.jet_wall[k] = q.jet_wall[k];
   }
   p.jet_mach = q.jet_mach; p.jet_rho = q.jet_rho; p.jet_T = q.jet_T;
   p.use_source = (tau_ref > 0 && std::isfinite(tau_ref)) ? 1 : 0;
+  p.src_implicit = s->num.source_implicit;
   p.tau_mode = q.tau_mode; p.tau_ref = tau_ref; p.rho_ref = q.rho_ref; p.T_ref = q.T_ref;
   p.sigma_lim = s->num.sigma_lim; p.kws = s->num.k_ws;
   p.limiter = s->num.limiter; p.flux = s->num.flux; p.fallback = s->num.positivity_fallback;
   if (q.dim == 2) { p.ntx = (q.nx + 15) / 16; p.nty = (q.ny + 14) / 15; }
-  else { p.ntx = (q.nx + 62) / 63; p.nty = 1; }
+  else { p.ntx = (q.nx + mx::tile_1d(64) - 1) / mx::tile_1d(64); p.nty = 1; }
   p.nblk = p.ntx * p.nty;
   p.ctrl = s->ctrl;
   return p;
@@ -318,9 +338,9 @@ static mx::BatchParams batch_params(maxent_solver* s) {
   std::memset(&p, 0, sizeof(p));
   p.plane = s->plane;
   p.inst = b->d_inst;
-  int k = b->nt == 64 ? 0 : (b->nt == 128 ? 1 : 2);
-  p.tiles = b->d_tiles[k];
-  p.n_tiles = b->n_tiles[k];
+  p.act_inst = b->d_act_inst;
+  p.act_tile0 = b->d_act_tile0;
+  p.bctrl = b->d_ctrl;
   p.cell_inst = b->d_cell_inst;
   p.bc_lo = s->prob.bc[0];
   p.bc_hi = s->prob.bc[1];
@@ -344,6 +364,22 @@ static int batch_reset(maxent_solver* s) {
   mx::BatchParams p = batch_params(s);
   p.Ub = s->U;
   HIP_TRY(s, mx::launch_batch_cfl(p, b->total, s->stream));
+  // instance queue: estimated work = cells x steps to t_end at the initial CFL rate
+  HIP_TRY(s, hipMemcpyAsync(b->h_inst, b->d_inst, b->n_inst * sizeof(mx::BatchInst), hipMemcpyDeviceToHost,
+                            s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  std::vector<double> work(b->n_inst);
+  for (int i = 0; i < b->n_inst; ++i) {
+    const mx::BatchInst& r = b->h_inst[i];
+    double rate = __builtin_bit_cast(double, r.maxrate);
+    double w = (double)r.n * r.t_end * rate / (s->num.cfl * r.dx);
+    work[i] = std::isfinite(w) ? w : 0.0;
+  }
+  for (int i = 0; i < b->n_inst; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  HIP_TRY(s, hipMemcpyAsync(b->d_order, b->order.data(), b->n_inst * sizeof(int), hipMemcpyHostToDevice,
+                            s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
   return MAXENT_OK;
 }
 
@@ -481,6 +517,8 @@ extern "C" int maxent_record(maxent_solver* s, int checkpoint_every, int max_ste
   if (s->batch) return fail(s, MAXENT_E_STATE, "the adjoint is not available for batch solvers");
   if (s->prob.system != 14) return fail(s, MAXENT_E_INVAL, "the adjoint needs the 14-moment system");
   if (s->num.precision != MAXENT_FP64) return fail(s, MAXENT_E_INVAL, "the adjoint needs FP64 precision");
+  if (s->num.source_implicit)
+    return fail(s, MAXENT_E_INVAL, "the adjoint needs the explicit BGK source (source_implicit = 0)");
   if (!s->ready) return fail(s, MAXENT_E_STATE, "record before a valid init_state");
   free_tape(s);
   TapeState* t = new (std::nothrow) TapeState();
@@ -710,7 +748,9 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   HIP_TRY(s, hipMemcpyAsync(g, t->grad, sizeof(g), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
   if (dJ_dparams) {
-    const bool jet = s->prob.bc[0] == MAXENT_BC_JET && s->prob.n_jets > 0;
+    bool jet = false;
+    for (int k = 0; k < 4; ++k) jet = jet || s->prob.bc[k] == MAXENT_BC_JET;
+    jet = jet && s->prob.n_jets > 0;
     dJ_dparams[0] = jet ? g[0] : 0.0;
     dJ_dparams[1] = jet ? g[1] : 0.0;
     dJ_dparams[2] = g[2];
@@ -772,7 +812,6 @@ extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_nu
   b->total = total;
   b->init.resize(n_inst);
   std::vector<int> cell_inst(total);
-  std::vector<int2> tiles[3];
   long long off = 0;
   for (int i = 0; i < n_inst; ++i) {
     mx::BatchInst r;
@@ -786,9 +825,6 @@ extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_nu
     r.fail_step = 0x7fffffff;
     b->init[i] = r;
     for (int c = 0; c < r.n; ++c) cell_inst[off + c] = i;
-    const int widths[3] = {63, 127, 255};
-    for (int k = 0; k < 3; ++k)
-      for (int st = 0; st < r.n; st += widths[k]) tiles[k].push_back(make_int2(i, st));
     off += r.n;
   }
   hipDeviceProp_t prop;
@@ -800,12 +836,12 @@ extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_nu
   if (e == hipSuccess) e = hipHostMalloc(&b->h_ctrl, sizeof(mx::BatchCtrl));
   if (e == hipSuccess) e = hipMalloc(&b->d_cell_inst, total * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(b->d_cell_inst, cell_inst.data(), total * sizeof(int), hipMemcpyHostToDevice);
-  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-    b->n_tiles[k] = (int)tiles[k].size();
-    e = hipMalloc(&b->d_tiles[k], tiles[k].size() * sizeof(int2));
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_tiles[k], tiles[k].data(), tiles[k].size() * sizeof(int2), hipMemcpyHostToDevice);
-  }
+  b->order.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) b->order[i] = i;
+  if (e == hipSuccess) e = hipMalloc(&b->d_order, n_inst * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(b->d_order, b->order.data(), n_inst * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&b->d_act_inst, n_inst * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&b->d_act_tile0, (n_inst + 1) * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(b->d_inst, b->init.data(), n_inst * sizeof(mx::BatchInst), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
@@ -827,15 +863,17 @@ static hipError_t batch_enqueue(maxent_solver* s, int steps, hipStream_t st) {
   const bool mid = s->num.integrator == MAXENT_MIDPOINT;
   const int prec = s->num.precision == MAXENT_MIXED ? 1 : 0;
   for (int k = 0; k < steps; ++k) {
-    hipError_t e = mx::launch_batch_finalize(b->d_inst, b->n_inst, s->num.cfl, b->d_ctrl, st);
+    hipError_t e = mx::launch_batch_finalize(b->d_inst, b->d_order, b->n_inst, s->num.cfl,
+                                             mx::tile_1d(b->nt * b->cpt), b->d_act_inst, b->d_act_tile0,
+                                             b->d_ctrl, st);
     if (e != hipSuccess) return e;
     p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
     p.mode = mx::MODE_EULER; p.cdt = mid ? 0.5 : 1.0; p.do_cfl = 0;
-    e = mx::launch_batch_stage(prec, b->nt, p, grid, st);
+    e = mx::launch_batch_stage(prec, b->nt, b->cpt, p, grid, st);
     if (e != hipSuccess) return e;
     p.Ub = s->Us; p.Ua = s->U; p.Uout = s->U;
     p.mode = mid ? mx::MODE_MID2 : mx::MODE_HEUN2; p.cdt = 1.0; p.do_cfl = 1;
-    e = mx::launch_batch_stage(prec, b->nt, p, grid, st);
+    e = mx::launch_batch_stage(prec, b->nt, b->cpt, p, grid, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -922,19 +960,22 @@ extern "C" int maxent_step_batch(maxent_solver* s, int max_steps, int chunk, max
   return MAXENT_OK;
 }
 
-extern "C" int maxent_set_batch_launch(maxent_solver* s, int threads, int wg_per_cu) {
+extern "C" int maxent_set_batch_launch(maxent_solver* s, int threads, int cells_per_thread, int wg_per_cu) {
   if (!s || !s->batch) return MAXENT_E_INVAL;
-  if (threads != 64 && threads != 128 && threads != 256) return fail(s, MAXENT_E_INVAL, "threads must be 64, 128 or 256");
+  if (!mx::batch_shape_supported(threads, cells_per_thread))
+    return fail(s, MAXENT_E_INVAL, "threads x cells per thread must be 64x1, 64x2, 64x4, 128x1, 128x2 or 256x1");
   if (wg_per_cu < 1 || wg_per_cu > 32) return fail(s, MAXENT_E_INVAL, "wg_per_cu must be 1..32");
   s->batch->nt = threads;
+  s->batch->cpt = cells_per_thread;
   s->batch->wg_per_cu = wg_per_cu;
   s->batch->graph_valid = false;
   return MAXENT_OK;
 }
 
-extern "C" int maxent_get_batch_launch(maxent_solver* s, int* threads, int* wg_per_cu) {
-  if (!s || !s->batch || !threads || !wg_per_cu) return MAXENT_E_INVAL;
+extern "C" int maxent_get_batch_launch(maxent_solver* s, int* threads, int* cells_per_thread, int* wg_per_cu) {
+  if (!s || !s->batch || !threads || !cells_per_thread || !wg_per_cu) return MAXENT_E_INVAL;
   *threads = s->batch->nt;
+  *cells_per_thread = s->batch->cpt;
   *wg_per_cu = s->batch->wg_per_cu;
   return MAXENT_OK;
 }
@@ -942,8 +983,8 @@ extern "C" int maxent_get_batch_launch(maxent_solver* s, int* threads, int* wg_p
 // Time `trial_steps` steps of every launch shape from the current state and keep the fastest
 // (cell-updates per second).  The state and the per-instance records are restored after each
 // trial, so the call leaves the solution untouched.
-extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* wg_per_cu,
-                                     double* best_rate) {
+extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* cells_per_thread,
+                                     int* wg_per_cu, double* best_rate) {
   if (!s || !s->batch) return MAXENT_E_INVAL;
   if (!s->ready) return fail(s, MAXENT_E_STATE, "autotune before a valid init_state");
   if (trial_steps < 1 || trial_steps > 10000) return fail(s, MAXENT_E_INVAL, "trial_steps must be 1..10000");
@@ -958,16 +999,17 @@ extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* thr
   e = hipMemcpyAsync(saveU, s->U, field, hipMemcpyDeviceToDevice, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(saveI, b->d_inst, recs, hipMemcpyDeviceToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  const int nts[3] = {64, 128, 256};
+  const int shapes[6][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
   const int wgs[4] = {2, 4, 8, 16};
   double best = -1.0;
-  int bt = b->nt, bw = b->wg_per_cu;
+  int bt = b->nt, bc = b->cpt, bw = b->wg_per_cu;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+  for (int a = 0; a < 6 && e == hipSuccess; ++a) {
     for (int w = 0; w < 4 && e == hipSuccess; ++w) {
-      b->nt = nts[a];
+      b->nt = shapes[a][0];
+      b->cpt = shapes[a][1];
       b->wg_per_cu = wgs[w];
       e = batch_enqueue(s, 1, s->stream);  // warm-up step (first use of the shape)
       if (e == hipSuccess) e = hipMemcpyAsync(s->U, saveU, field, hipMemcpyDeviceToDevice, s->stream);
@@ -983,7 +1025,7 @@ extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* thr
       long long cu = 0;
       for (int i = 0; i < b->n_inst; ++i) cu += b->h_inst[i].step * (long long)b->h_inst[i].n;
       double rate = ms > 0 ? cu / (ms * 1e-3) : 0.0;
-      if (rate > best) { best = rate; bt = nts[a]; bw = wgs[w]; }
+      if (rate > best) { best = rate; bt = shapes[a][0]; bc = shapes[a][1]; bw = wgs[w]; }
       e = hipMemcpyAsync(s->U, saveU, field, hipMemcpyDeviceToDevice, s->stream);
       if (e == hipSuccess) e = hipMemcpyAsync(b->d_inst, saveI, recs, hipMemcpyDeviceToDevice, s->stream);
     }
@@ -995,11 +1037,13 @@ extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* thr
   (void)hipFree(saveI);
   if (e != hipSuccess) return fail(s, MAXENT_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   b->nt = bt;
+  b->cpt = bc;
   b->wg_per_cu = bw;
   b->graph_valid = false;
   // counters polluted by the trials
   HIP_TRY(s, mx::launch_ctrl_reset(s->ctrl, 0.0, s->stream));
   if (threads) *threads = bt;
+  if (cells_per_thread) *cells_per_thread = bc;
   if (wg_per_cu) *wg_per_cu = bw;
   if (best_rate) *best_rate = best;
   return MAXENT_OK;

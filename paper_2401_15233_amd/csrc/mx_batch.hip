@@ -1,15 +1,15 @@
 // Batched independent 1D shock tubes in one launch per stage.
 //
 // Many 1D problems of uneven length, each with its own collision time, end time and CFL time
-// step, are concatenated in one structure-of-arrays field.  Each instance is cut into tiles
-// of TX cells (tiles never straddle instances); the tile list is static.  A persistent
-// launch of a fixed number of workgroups sweeps the tile list with a grid stride, skipping
-// the tiles of instances that have reached their end time, so finished instances cost a
-// load and a compare; every workgroup leaves the loop when the list is exhausted.  A step is
-// finalize (per-instance dt) + two stage launches, so a chunk of steps can be captured once
-// in a hipGraph and replayed.  The per-cell arithmetic is the single-instance 1D kernel's
-// (same device functions, same update formula), so a batched instance reproduces the same
-// instance run alone bit for bit.
+// step, are concatenated in one structure-of-arrays field.  The instances form a queue
+// ordered by estimated work (cells x steps, from the initial CFL rate).  Each step, a
+// one-workgroup finalize kernel gives every instance its time step and compacts the
+// instances that still advance, in queue order, into a work list of tiles (tiles never
+// straddle instances); the two stage launches of the step split that list into contiguous
+// ranges, one per workgroup, so finished instances cost nothing.  A step is finalize + two
+// stage launches, so a chunk of steps can be captured once in a hipGraph and replayed.  The
+// per-cell arithmetic is the single-instance 1D kernel's (same device functions, same update
+// formula), so a batched instance reproduces the same instance run alone bit for bit.
 #include "mx_internal.hpp"
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
@@ -46,40 +46,78 @@ __device__ __forceinline__ int bmap(int g, int n, int lo, int hi, int& refl) {
   return g < 0 ? 0 : (g >= n ? n - 1 : g);
 }
 
-// one thread per instance: time step from the instance's CFL rate, clipped to its t_end
-__global__ void batch_finalize_kernel(BatchInst* in, int n_inst, double cfl, BatchCtrl* bc) {
-  __shared__ int s_active;
-  if (threadIdx.x == 0) s_active = 0;
+// One workgroup of 1024 threads walks the instance queue (instances ordered by estimated
+// work): time step of each instance from its CFL rate, clipped to its t_end; then an ordered
+// compaction of the instances that advance, with the exclusive prefix of their tile counts.
+// The stage launches of the step split the resulting tile list into contiguous ranges.
+__global__ __launch_bounds__(1024) void batch_finalize_kernel(BatchInst* in, const int* order, int n_inst,
+                                                             double cfl, int tile_w, int* act_inst,
+                                                             int* act_tile0, BatchCtrl* bc) {
+  __shared__ int s_wave[16][2];   // per-wavefront totals of (active, tiles)
+  __shared__ int s_carry[2];      // totals of the earlier chunks
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  if (t == 0) { s_carry[0] = 0; s_carry[1] = 0; }
   __syncthreads();
-  int active = 0;
-  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
-    BatchInst& c = in[i];
-    double dt = 0.0;
-    if (c.status == 0) {
-      double m = __longlong_as_double((long long)c.maxrate);
-      dt = (m > 0.0) ? cfl * c.dx / m : 0.0;
-      if (c.t >= c.t_end * (1.0 - 1e-14)) dt = 0.0;
-      else dt = fmin(dt, c.t_end - c.t);
+  for (int base = 0; base < n_inst; base += 1024) {
+    const int q = base + t;
+    int a = 0, nt = 0, inst = 0;
+    if (q < n_inst) {
+      inst = order[q];
+      BatchInst& c = in[inst];
+      double dt = 0.0;
+      if (c.status == 0) {
+        double m = __longlong_as_double((long long)c.maxrate);
+        dt = (m > 0.0) ? cfl * c.dx / m : 0.0;
+        if (c.t >= c.t_end * (1.0 - 1e-14)) dt = 0.0;
+        else dt = fmin(dt, c.t_end - c.t);
+      }
+      c.dt = dt;
+      c.maxrate = 0ull;
+      if (dt > 0.0) {
+        c.t += dt;
+        c.step += 1;
+        c.dt_last = dt;
+        a = 1;
+        nt = (c.n + tile_w - 1) / tile_w;
+      }
     }
-    c.dt = dt;
-    c.maxrate = 0ull;
-    if (dt > 0.0) {
-      c.t += dt;
-      c.step += 1;
-      c.dt_last = dt;
-      ++active;
+    // inclusive scans within the wavefront
+    int sa = a, sn = nt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int ya = __shfl_up(sa, o, 64), yn = __shfl_up(sn, o, 64);
+      if (lane >= o) { sa += ya; sn += yn; }
     }
+    if (lane == 63) { s_wave[wid][0] = sa; s_wave[wid][1] = sn; }
+    __syncthreads();
+    int oa = s_carry[0], on = s_carry[1];
+    for (int w = 0; w < wid; ++w) { oa += s_wave[w][0]; on += s_wave[w][1]; }
+    if (a) {
+      act_inst[oa + sa - 1] = inst;
+      act_tile0[oa + sa - 1] = on + sn - nt;
+    }
+    __syncthreads();  // every thread has read s_carry
+    if (t == 1023) { s_carry[0] = oa + sa; s_carry[1] = on + sn; }
+    __syncthreads();
   }
-  active = bwave_sum(active);
-  if ((threadIdx.x & 63) == 0 && active) atomicAdd(&s_active, active);
-  __syncthreads();
-  if (threadIdx.x == 0) bc->n_active = s_active;
+  if (t == 0) {
+    act_tile0[s_carry[0]] = s_carry[1];
+    bc->n_active = s_carry[0];
+    bc->n_tiles = s_carry[1];
+  }
 }
 
-template <class SYS, int ORDER, int PREC, int NT>
-__global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
+// Stage kernel: a workgroup of NT threads owns tiles of CPT * NT - 4 cells (CPT cells per
+// thread), so the tile plus its two-cell halos fills whole rounds over the threads.  The
+// step's tile list (active instances in queue order, each cut into tiles) is split into
+// contiguous ranges, one per workgroup, with an XCD-aware order of the ranges; a workgroup
+// finds its first tile by a binary search over the tile prefix and then walks forward.
+// Two waves per SIMD: the register budget is 256 per lane.
+template <class SYS, int ORDER, int PREC, int NT, int CPT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void batch_stage_kernel(BatchParams p) {
   constexpr int NV = SYS::NV;
-  constexpr int TX = NT - 1;
+  constexpr int TX = tile_1d(CPT * NT);
   constexpr int G = (ORDER == 2) ? 2 : 1;
   constexpr int LX = TX + 2 * G;
   constexpr int NFX = TX + 1;
@@ -92,16 +130,41 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
 
-  for (int k = blockIdx.x; k < p.n_tiles; k += gridDim.x) {
-    const int2 tl = p.tiles[k];
-    const int inst = tl.x;
-    const int i0 = tl.y;
+  const int n_tiles = p.bctrl->n_tiles;
+  const int n_act = p.bctrl->n_active;
+  const int nb = gridDim.x;
+  // hardware deals consecutive workgroups round-robin to the 8 XCDs: give each XCD a band of
+  // neighbouring ranges, so that halos and instance records are shared in its L2
+  const int slot = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int per = (n_tiles + nb - 1) / nb;
+  const int k0 = slot * per;
+  const int k1 = min(k0 + per, n_tiles);
+  if (k0 >= k1) return;  // uniform over the workgroup
+  int j = 0;
+  {
+    int hi = n_act - 1;  // last active instance whose first tile is <= k0
+    while (j < hi) {
+      const int mid = (j + hi + 1) >> 1;
+      if (p.act_tile0[mid] <= k0) j = mid;
+      else hi = mid - 1;
+    }
+  }
+  int first = p.act_tile0[j], next = p.act_tile0[j + 1];
+
+  for (int k = k0; k < k1; ++k) {
+    if (k >= next) {  // every active instance has at least one tile
+      ++j;
+      first = next;
+      next = p.act_tile0[j + 1];
+    }
+    const int inst = p.act_inst[j];
+    const int i0 = (k - first) * TX;
     BatchInst* c = p.inst + inst;
     const double dt = c->dt;
-    if (!(dt > 0.0)) continue;  // uniform over the workgroup: instance finished or failed
+    if (!(dt > 0.0)) continue;  // uniform; not reached for a listed instance
     const int n = c->n;
     const long long off = c->off;
-    const double dx = c->dx, inv_dx = c->inv_dx;
+    const double inv_dx = c->inv_dx;
     __syncthreads();            // LDS of the previous tile is no longer read
     if (t < 3) sFlag[t] = 0;
     int n64 = 0;
@@ -152,9 +215,8 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
       __syncthreads();
     }
 
-    // 3. faces
-    {
-      const int fi = t;
+    // 3. faces: face fi lies between tile cells fi - 1 and fi
+    for (int fi = t; fi < NFX; fi += NT) {
       double WL[NV], WR[NV];
       if constexpr (ORDER == 2) {
         double A[NV], B[NV], C[NV], D[NV];
@@ -175,8 +237,9 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
     // 4. update
     int flag = 0;
     double rate = 0.0;
-    if (t < TX && i0 + t < n) {
-      long long g = off + i0 + t;
+    for (int ci = t; ci < TX; ci += NT) {
+      if (i0 + ci >= n) break;
+      long long g = off + i0 + ci;
       double Ub[NV], W[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + g];
@@ -195,7 +258,7 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double L = -(sFx[v * NFX + t + 1] - sFx[v * NFX + t]) * inv_dx;
+        double L = -(sFx[v * NFX + ci + 1] - sFx[v * NFX + ci]) * inv_dx;
         L = L + Cs[v];
         double o;
         if (p.mode == MODE_EULER) o = Ub[v] + (p.cdt * dt) * L;
@@ -211,7 +274,7 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
       SYS::cons_to_prim(Un, Wn);
       if (!fin) flag |= ST_NONFINITE;
       else if (!SYS::admissible(Wn)) flag |= ST_UNREALIZABLE;
-      if (p.do_cfl && flag == 0) rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws);
+      else if (p.do_cfl) rate = fmax(rate, SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws));
     }
     flag = bwave_or(flag);
     nfb = bwave_sum(nfb);
@@ -245,6 +308,7 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(BatchParams p) {
   }
 }
 
+
 // CFL rate of every instance's current state (after init)
 template <class SYS>
 __global__ __launch_bounds__(256) void batch_cfl_kernel(BatchParams p, long long total) {
@@ -261,27 +325,36 @@ __global__ __launch_bounds__(256) void batch_cfl_kernel(BatchParams p, long long
   }
 }
 
-template <int PREC, int NT>
+template <int PREC, int NT, int CPT>
 static hipError_t launch_bs(const BatchParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((batch_stage_kernel<Sys14, 2, PREC, NT>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((batch_stage_kernel<Sys14, 2, PREC, NT, CPT>), dim3(grid), dim3(NT), 0, s, p);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_stage(int precision, int nt, const BatchParams& p, int grid, hipStream_t s) {
-  if (precision == 0) {
-    if (nt == 64) return launch_bs<0, 64>(p, grid, s);
-    if (nt == 128) return launch_bs<0, 128>(p, grid, s);
-    if (nt == 256) return launch_bs<0, 256>(p, grid, s);
-  } else {
-    if (nt == 64) return launch_bs<1, 64>(p, grid, s);
-    if (nt == 128) return launch_bs<1, 128>(p, grid, s);
-    if (nt == 256) return launch_bs<1, 256>(p, grid, s);
-  }
+template <int PREC>
+static hipError_t launch_bs_p(int nt, int cpt, const BatchParams& p, int grid, hipStream_t s) {
+  if (nt == 64 && cpt == 1) return launch_bs<PREC, 64, 1>(p, grid, s);
+  if (nt == 64 && cpt == 2) return launch_bs<PREC, 64, 2>(p, grid, s);
+  if (nt == 64 && cpt == 4) return launch_bs<PREC, 64, 4>(p, grid, s);
+  if (nt == 128 && cpt == 1) return launch_bs<PREC, 128, 1>(p, grid, s);
+  if (nt == 128 && cpt == 2) return launch_bs<PREC, 128, 2>(p, grid, s);
+  if (nt == 256 && cpt == 1) return launch_bs<PREC, 256, 1>(p, grid, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_finalize(BatchInst* in, int n_inst, double cfl, BatchCtrl* bc, hipStream_t s) {
-  hipLaunchKernelGGL(batch_finalize_kernel, dim3(1), dim3(1024), 0, s, in, n_inst, cfl, bc);
+bool batch_shape_supported(int nt, int cpt) {
+  return (nt == 64 && (cpt == 1 || cpt == 2 || cpt == 4)) || (nt == 128 && (cpt == 1 || cpt == 2)) ||
+         (nt == 256 && cpt == 1);
+}
+
+hipError_t launch_batch_stage(int precision, int nt, int cpt, const BatchParams& p, int grid, hipStream_t s) {
+  return precision == 0 ? launch_bs_p<0>(nt, cpt, p, grid, s) : launch_bs_p<1>(nt, cpt, p, grid, s);
+}
+
+hipError_t launch_batch_finalize(BatchInst* in, const int* order, int n_inst, double cfl, int tile_w,
+                                 int* act_inst, int* act_tile0, BatchCtrl* bc, hipStream_t s) {
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(1), dim3(1024), 0, s, in, order, n_inst, cfl, tile_w,
+                     act_inst, act_tile0, bc);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ struct BatchInst {
 };
 
 struct BatchCtrl {
-  int n_active;                  // instances that advanced in the last finalize
+  int n_active;                  // instances that advance in the current step
+  int n_tiles;                   // their tiles: the work list of the step's stage launches
 };
 
 struct BatchParams {
@@ -27,8 +28,9 @@ struct BatchParams {
   double* Uout;
   long long plane;               // padded total cells
   BatchInst* inst;
-  const int2* tiles;             // (instance, first local cell) of every tile
-  int n_tiles;
+  const int* act_inst;           // instances that advance, in queue order
+  const int* act_tile0;          // first work-list tile of each; [n_active] = n_tiles
+  const BatchCtrl* bctrl;        // n_active and n_tiles of the current step
   const int* cell_inst;          // instance of every cell (CFL initialisation)
   int bc_lo, bc_hi;
   int tau_mode;
@@ -41,8 +43,11 @@ struct BatchParams {
   DevCtrl* ctrl;                 // shared counters (fallbacks, FP64 re-evaluations)
 };
 
-hipError_t launch_batch_stage(int precision, int nt, const BatchParams& p, int grid, hipStream_t s);
-hipError_t launch_batch_finalize(BatchInst* in, int n_inst, double cfl, BatchCtrl* bc, hipStream_t s);
+// launch shapes: nt threads per workgroup, cpt cells per thread (tiles of tile_1d(nt * cpt))
+bool batch_shape_supported(int nt, int cpt);
+hipError_t launch_batch_stage(int precision, int nt, int cpt, const BatchParams& p, int grid, hipStream_t s);
+hipError_t launch_batch_finalize(BatchInst* in, const int* order, int n_inst, double cfl, int tile_w,
+                                 int* act_inst, int* act_tile0, BatchCtrl* bc, hipStream_t s);
 hipError_t launch_batch_cfl(const BatchParams& p, long long total, hipStream_t s);
 
 }  // namespace mx

@@ -1,8 +1,9 @@
 // Boundary conditions of the finite-volume stencil: every cell index outside the domain
 // (ghost cell) is mapped to a primitive state when the stencil is loaded, so ghost cells are
 // never stored.  Transmissive: copy of the edge cell; periodic: wrap; reflective: mirror
-// image with the components odd under the reflection negated; jet inflow (left wall,
-// 14 moments): the Maxwellian jet state inside each jet's band of rows, transmissive outside.
+// image with the components odd under the reflection negated; jet inflow (any wall,
+// 14 moments): the Maxwellian jet state in the ghost cells along each jet's band of the
+// wall, transmissive outside.
 // Used by the forward stage kernels and by the reverse (adjoint) kernels.
 #pragma once
 #include "mx_internal.hpp"
@@ -23,12 +24,15 @@ __device__ __forceinline__ int map_axis(int g, int n, int lo, int hi, int& refl)
   return g < 0 ? 0 : (g >= n ? n - 1 : g);
 }
 
-// the jet whose band holds row sj (the last one listed if bands overlap), or -1
-__device__ __forceinline__ int jet_of_row(const StageParams& p, int sj) {
-  double yc = p.y0 + ((double)sj + 0.5) * p.dy;
+// the jet on `wall` (0 x-low, 1 x-high, 2 y-low, 3 y-high) whose band holds boundary cell s
+// (a row for the x walls, a column for the y walls; the last jet listed if bands overlap),
+// or -1
+__device__ __forceinline__ int jet_on_wall(const StageParams& p, int wall, int s) {
+  const double c = (wall < 2) ? p.y0 + ((double)s + 0.5) * p.dy : p.x0 + ((double)s + 0.5) * p.dx;
   int hit = -1;
   for (int k = 0; k < p.n_jets; ++k)
-    if (yc >= p.jet_yc[k] - 0.5 * p.jet_w[k] && yc <= p.jet_yc[k] + 0.5 * p.jet_w[k]) hit = k;
+    if (p.jet_wall[k] == wall && c >= p.jet_yc[k] - 0.5 * p.jet_w[k] && c <= p.jet_yc[k] + 0.5 * p.jet_w[k])
+      hit = k;
   return hit;
 }
 
@@ -69,8 +73,12 @@ __device__ __forceinline__ void load_prims(const StageParams& p, const double* U
       if (SYS::odd(v, 1)) W[v] = -W[v];
   }
   if constexpr (NV == 14) {
-    if (gi < 0 && p.bc[0] == 3) {
-      int k = jet_of_row(p, sj);
+    if (p.n_jets > 0) {
+      int k = -1;
+      if (gi < 0 && p.bc[0] == 3) k = jet_on_wall(p, 0, sj);
+      else if (gi >= p.nx && p.bc[1] == 3) k = jet_on_wall(p, 1, sj);
+      else if (gj < 0 && p.bc[2] == 3) k = jet_on_wall(p, 2, si);
+      else if (gj >= p.ny && p.bc[3] == 3) k = jet_on_wall(p, 3, si);
       if (k >= 0) jet_state(p, k, W);
     }
   }

@@ -21,6 +21,11 @@ struct DevCtrl {
   long long n_states;            // mixed precision: face states evaluated
 };
 
+// 1D tiles: a workgroup of NT threads owns NT - 4 cells, so that the cells plus the two-cell
+// halo on each side (NT), the limiter items (NT - 2) and the faces (NT - 3) each take a single
+// round over the threads.
+constexpr int tile_1d(int nt) { return nt - 4; }
+
 enum { MODE_EULER = 0, MODE_HEUN2 = 1, MODE_MID2 = 2 };
 enum { ST_NONFINITE = 1, ST_UNREALIZABLE = 2 };
 
@@ -33,9 +38,11 @@ struct StageParams {
   double x0, y0, dx, dy, inv_dx, inv_dy;
   int bc[4];
   int n_jets;
-  double jet_yc[4], jet_w[4], jet_ang[4];
+  double jet_yc[4], jet_w[4], jet_ang[4];   // centre along the jet's wall, width, angle
+  int jet_wall[4];         // 0 x-low, 1 x-high, 2 y-low, 3 y-high
   double jet_mach, jet_rho, jet_T;
   int use_source, tau_mode;
+  int src_implicit;        // BGK source by backward Euler on the transported state (EULER mode)
   double tau_ref, rho_ref, T_ref;
   double sigma_lim, kws;
   int limiter, flux, fallback;

@@ -13,7 +13,8 @@
 //      writes the result, checks it (non-finite, rho <= 0, P not SPD) and, in the last
 //      stage of a step, reduces the CFL rate of the new state for the next step.
 // The 2D tile is 16 x 15 cells for 256 threads: 255 x-faces and 256 y-faces, one of each
-// per thread.  The 1D tile is 63 cells for one 64-wide wavefront: 64 faces.
+// per thread.  The 1D tile is 60 cells for one 64-wide wavefront: cells plus halo fill the
+// wavefront exactly.
 #include "mx_internal.hpp"
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
@@ -199,7 +200,8 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + off];
       SYS::cons_to_prim(Ub, W);
       double Cs[NV];
-      if (p.use_source) {
+      const bool explicit_src = p.use_source && !p.src_implicit;
+      if (explicit_src) {
         double rho = W[0];
         double T = SYS::pressure(W) / rho;
         double tau = (p.tau_mode == 0) ? p.tau_ref * (p.rho_ref / rho) * sqrt(p.T_ref / T) : p.tau_ref;
@@ -220,8 +222,26 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         else if (p.mode == MODE_HEUN2) o = 0.5 * p.Ua[v * p.plane + off] + 0.5 * (Ub[v] + dt * L);
         else o = p.Ua[v * p.plane + off] + dt * L;
         Un[v] = o;
-        p.Uout[v * p.plane + off] = o;
       }
+      if (p.use_source && p.src_implicit) {
+        // backward-Euler BGK relaxation of the transported state (forward-Euler stages only):
+        // the source keeps rho, rho u and the energy, so the Maxwellian and tau of the new
+        // state are those of the transported state, and U_new = (U_t + h U_eq) / (1 + h),
+        // h = dt / tau
+        double Wt[NV], We[NV], Ue[NV];
+        SYS::cons_to_prim(Un, Wt);
+        const double rho = Wt[0];
+        const double T = SYS::pressure(Wt) / rho;
+        const double tau = (p.tau_mode == 0) ? p.tau_ref * (p.rho_ref / rho) * sqrt(p.T_ref / T) : p.tau_ref;
+        const double h = (p.cdt * dt) / tau;
+        const double w = 1.0 / (1.0 + h);
+        SYS::equilibrium(Wt, We);
+        SYS::prim_to_cons(We, Ue);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Un[v] = (Un[v] + h * Ue[v]) * w;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) p.Uout[v * p.plane + off] = Un[v];
       bool fin = true;
 #pragma unroll
       for (int v = 0; v < NV; ++v) fin = fin && isfinite(Un[v]);
@@ -412,7 +432,7 @@ static hipError_t launch_stage_t(const StageParams& p, hipStream_t s) {
   if constexpr (DIM == 2) {
     hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, PREC, 16, 15, 256>), dim3(grid), dim3(256), 0, s, p);
   } else {
-    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, PREC, 63, 1, 64>), dim3(grid), dim3(64), 0, s, p);
+    hipLaunchKernelGGL((stage_kernel<SYS, DIM, ORDER, PREC, tile_1d(64), 1, 64>), dim3(grid), dim3(64), 0, s, p);
   }
   return hipGetLastError();
 }

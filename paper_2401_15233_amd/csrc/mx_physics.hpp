@@ -481,6 +481,16 @@ struct Sys14 {
     return k.sig;
   }
 
+  // local Maxwellian of a state: same rho, u and p, P = p I, q = 0, R = 15 p^2 / rho (the
+  // state the BGK source relaxes to; it has the same rho, rho u and energy)
+  template <class T> MX_HD static void equilibrium(const T* W, T* We) {
+    T p = (W[4] + W[7] + W[9]) * T(1.0 / 3.0);
+    We[0] = W[0]; We[1] = W[1]; We[2] = W[2]; We[3] = W[3];
+    We[4] = p; We[5] = T(0); We[6] = T(0); We[7] = p; We[8] = T(0); We[9] = p;
+    We[10] = T(0); We[11] = T(0); We[12] = T(0);
+    We[13] = mdiv(T(15) * p * p, W[0]);
+  }
+
   // BGK source; inv_tau = 1/tau at the cell centre
   template <class T> MX_HD static void source(const T* W, T inv_tau, T* C) {
     T rho = W[0];
@@ -627,6 +637,12 @@ struct Sys5 {
     Core<T> k;
     core(W, T(0), k);
     return k.sig;
+  }
+
+  // 1D1V local Maxwellian: same rho, u, P; q = 0, r = 3 P^2 / rho
+  template <class T> MX_HD static void equilibrium(const T* W, T* We) {
+    We[0] = W[0]; We[1] = W[1]; We[2] = W[2]; We[3] = T(0);
+    We[4] = mdiv(T(3) * W[2] * W[2], W[0]);
   }
 
   template <class T> MX_HD static void source(const T* W, T inv_tau, T* C) {

@@ -209,6 +209,19 @@ def crossed_jets_initial(nx, ny):
     return uniform_prims14(nx, ny, JET_DEFAULTS['background_rho'], JET_DEFAULTS['background_T'])
 
 
+# The paper's own crossed jets (Section 6): unit square, two M = 5 jets of width L/7 centred
+# on the left and bottom walls, pointing to the centre (at a right angle to each other),
+# into a background at 1e-5 of the jet density; forward Euler, CFL 0.5, collisionless.
+# Walls: 'xlo' = left, 'ylo' = bottom.
+PAPER_JETS = dict(mach=5.0, rho=1.0, T=1.0, background_rho=1e-5, background_T=1.0,
+                  jets=((0.5, 1.0 / 7.0, 0.0, 'xlo'), (0.5, 1.0 / 7.0, 90.0, 'ylo')))
+
+
+def paper_jets_initial(nx, ny):
+    """Start of the paper's crossed jets: uniform Maxwellian background at rest."""
+    return uniform_prims14(nx, ny, PAPER_JETS['background_rho'], PAPER_JETS['background_T'])
+
+
 def crossed_jets_developed(nx, ny, seed=0, reach=0.6, smear=0.02):
     """A synthetic mid-run crossed-jets field: two Maxwellian beams (M = 3, T = 1) that have
     penetrated to x = reach from the left wall along +-30 degrees, smoothly tapered, over

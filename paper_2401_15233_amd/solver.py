@@ -16,6 +16,7 @@ MAXENT_OK = 0
 STATUS = {-1: 'INVAL', -2: 'NOMEM', -3: 'DEVICE', -4: 'NONFINITE', -5: 'UNREALIZABLE',
           -6: 'STATE'}
 BC = {'transmissive': 0, 'periodic': 1, 'reflective': 2, 'jet': 3}
+WALL = {'xlo': 0, 'xhi': 1, 'ylo': 2, 'yhi': 3}
 LIMITER = {'minmod': 0, 'vanalbada': 1}
 FLUX = {'hll': 0, 'rusanov': 1}
 INTEGRATOR = {'fe': 0, 'ssprk2': 1, 'midpoint': 2}
@@ -48,14 +49,15 @@ class Problem(ctypes.Structure):
                 ('jet_width', ctypes.c_double * 4), ('jet_angle_deg', ctypes.c_double * 4),
                 ('jet_mach', ctypes.c_double), ('jet_rho', ctypes.c_double),
                 ('jet_T', ctypes.c_double), ('tau_mode', ctypes.c_int),
-                ('rho_ref', ctypes.c_double), ('T_ref', ctypes.c_double)]
+                ('rho_ref', ctypes.c_double), ('T_ref', ctypes.c_double),
+                ('jet_wall', ctypes.c_int * 4)]
 
 
 class Numerics(ctypes.Structure):
     _fields_ = [('precision', ctypes.c_int), ('order', ctypes.c_int), ('limiter', ctypes.c_int),
                 ('flux', ctypes.c_int), ('integrator', ctypes.c_int), ('cfl', ctypes.c_double),
                 ('sigma_lim', ctypes.c_double), ('k_ws', ctypes.c_double),
-                ('positivity_fallback', ctypes.c_int)]
+                ('positivity_fallback', ctypes.c_int), ('source_implicit', ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -122,10 +124,10 @@ def load_library(path=LIB_PATH):
                                       ctypes.POINTER(Instance), vp, ctypes.POINTER(vp)]
     L.maxent_step_batch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(BatchInfo),
                                     ctypes.POINTER(InstanceInfo)]
-    L.maxent_set_batch_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
-    L.maxent_get_batch_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
-    L.maxent_autotune_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    L.maxent_set_batch_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    pint = ctypes.POINTER(ctypes.c_int)
+    L.maxent_get_batch_launch.argtypes = [vp, pint, pint, pint]
+    L.maxent_autotune_batch.argtypes = [vp, ctypes.c_int, pint, pint, pint, ctypes.POINTER(ctypes.c_double)]
     L.maxent_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong)]
     L.maxent_record.argtypes = [vp, ctypes.c_int, ctypes.c_int]
@@ -154,8 +156,12 @@ def make_problem(system=14, dim=1, nx=100, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
     for k, b in enumerate(bc):
         p.bc[k] = BC[b] if isinstance(b, str) else int(b)
     p.n_jets = len(jets)
-    for k, (yc, w, ang) in enumerate(jets):
-        p.jet_yc[k], p.jet_width[k], p.jet_angle_deg[k] = yc, w, ang
+    for k, jet in enumerate(jets):
+        # (centre along the wall, width, angle in degrees[, wall]); wall 0 x-low (default),
+        # 1 x-high, 2 y-low, 3 y-high, or its name
+        p.jet_yc[k], p.jet_width[k], p.jet_angle_deg[k] = jet[:3]
+        w = jet[3] if len(jet) > 3 else 0
+        p.jet_wall[k] = WALL[w] if isinstance(w, str) else int(w)
     p.jet_mach, p.jet_rho, p.jet_T = jet_mach, jet_rho, jet_T
     p.tau_mode = TAU_MODE[tau_mode] if isinstance(tau_mode, str) else int(tau_mode)
     p.rho_ref, p.T_ref = rho_ref, T_ref
@@ -163,7 +169,7 @@ def make_problem(system=14, dim=1, nx=100, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
 
 
 def make_numerics(precision='fp64', order=2, limiter='minmod', flux='hll', integrator='ssprk2',
-                  cfl=0.5, sigma_lim=1e-4, k_ws=1.0, positivity_fallback=True):
+                  cfl=0.5, sigma_lim=1e-4, k_ws=1.0, positivity_fallback=True, source_implicit=False):
     n = Numerics()
     n.precision = PRECISION[precision]
     n.order = order
@@ -172,6 +178,7 @@ def make_numerics(precision='fp64', order=2, limiter='minmod', flux='hll', integ
     n.integrator = INTEGRATOR[integrator]
     n.cfl, n.sigma_lim, n.k_ws = cfl, sigma_lim, k_ws
     n.positivity_fallback = int(bool(positivity_fallback))
+    n.source_implicit = int(bool(source_implicit))
     return n
 
 
@@ -361,19 +368,22 @@ class MaxEntBatch(MaxEntSolver):
                           for i in range(self.n_inst)]
         return d
 
-    def set_launch(self, threads, wg_per_cu):
-        self._check(self._lib.maxent_set_batch_launch(self._h, int(threads), int(wg_per_cu)))
+    def set_launch(self, threads, cells_per_thread, wg_per_cu):
+        self._check(self._lib.maxent_set_batch_launch(self._h, int(threads), int(cells_per_thread),
+                                                      int(wg_per_cu)))
 
     def launch(self):
-        a, b = ctypes.c_int(), ctypes.c_int()
-        self._check(self._lib.maxent_get_batch_launch(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        a, c, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.maxent_get_batch_launch(self._h, ctypes.byref(a), ctypes.byref(c),
+                                                      ctypes.byref(b)))
+        return a.value, c.value, b.value
 
     def autotune(self, trial_steps=20):
-        a, b, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        a, c, b, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self._check(self._lib.maxent_autotune_batch(self._h, int(trial_steps), ctypes.byref(a),
-                                                    ctypes.byref(b), ctypes.byref(r)))
-        return {'threads': a.value, 'wg_per_cu': b.value, 'cell_updates_per_s': r.value}
+                                                    ctypes.byref(c), ctypes.byref(b), ctypes.byref(r)))
+        return {'threads': a.value, 'cells_per_thread': c.value, 'wg_per_cu': b.value,
+                'cell_updates_per_s': r.value}
 
     def split(self, field):
         """Per-instance views [14][n_i] of a concatenated field."""

@@ -8,7 +8,9 @@ from oracle import scheme as sc, moments as mo
 
 SOLVER_TO_SETUP = ('system', 'dim', 'nx', 'ny', 'x0', 'x1', 'y0', 'y1', 'jet_mach', 'jet_rho',
                    'jet_T', 'tau_mode', 'rho_ref', 'T_ref', 'order', 'limiter', 'flux',
-                   'integrator', 'cfl', 'sigma_lim', 'k_ws', 'positivity_fallback')
+                   'integrator', 'cfl', 'sigma_lim', 'k_ws', 'positivity_fallback',
+                   'source_implicit')
+WALLS = {'xlo': 0, 'xhi': 1, 'ylo': 2, 'yhi': 3}
 
 
 def to_setup(kw):
@@ -19,7 +21,7 @@ def to_setup(kw):
     if 'bc' in kw:
         s.bc = tuple(kw['bc'])
     if 'jets' in kw:
-        s.jets = [tuple(j) for j in kw['jets']]
+        s.jets = [tuple(j[:3]) + ((WALLS.get(j[3], j[3]),) if len(j) > 3 else ()) for j in kw['jets']]
     return s
 
 

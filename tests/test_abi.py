@@ -34,14 +34,16 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.maxent_abi_version() == 1
+    assert lib.maxent_abi_version() == 2
 
 
 def test_struct_layouts_match_header():
     """ctypes mirrors of the header structs have the C layout (size and field offsets)."""
-    assert ctypes.sizeof(S.Problem) == 4 * 4 + 4 * 8 + 4 * 4 + 4 + 4 + 12 * 8 + 3 * 8 + 8 + 2 * 8
+    assert ctypes.sizeof(S.Problem) == 4 * 4 + 4 * 8 + 4 * 4 + 4 + 4 + 12 * 8 + 3 * 8 + 8 + 2 * 8 + 4 * 4
     assert S.Problem.x0.offset == 16 and S.Problem.n_jets.offset == 64
-    assert ctypes.sizeof(S.Numerics) == 5 * 4 + 4 + 3 * 8 + 8
+    assert S.Problem.jet_wall.offset == 216
+    assert ctypes.sizeof(S.Numerics) == 5 * 4 + 4 + 3 * 8 + 4 + 4
+    assert S.Numerics.source_implicit.offset == 52
     assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
 
 
@@ -50,6 +52,12 @@ def test_struct_layouts_match_header():
     dict(bc=('periodic', 'transmissive', 'transmissive', 'transmissive')),
     dict(dim=2, ny=8, bc=('transmissive', 'jet', 'transmissive', 'transmissive')),
     dict(bc=('jet', 'transmissive', 'transmissive', 'transmissive')),
+    dict(dim=2, ny=8, bc=('jet', 'transmissive', 'transmissive', 'transmissive'),
+         jets=[(0.5, 0.2, 0.0, 'ylo')]),                      # the jet's wall is not JET
+    dict(dim=2, ny=8, bc=('jet', 'transmissive', 'jet', 'transmissive'),
+         jets=[(0.5, 0.2, 0.0, 'xlo')]),                      # a JET side without a jet
+    dict(dim=2, ny=8, bc=('jet', 'transmissive', 'transmissive', 'transmissive'),
+         jets=[(0.5, 0.2, 0.0, 7)]),                          # no such wall
     dict(x1=-1.0)])
 def test_create_rejects_bad_problem(lib, bad):
     kw = dict(system=14, dim=1, nx=16, ny=1)
@@ -63,7 +71,8 @@ def test_create_rejects_bad_problem(lib, bad):
 
 
 @pytest.mark.parametrize('bad', [dict(order=3), dict(cfl=0.0), dict(cfl=1.5), dict(sigma_lim=0.0),
-                                 dict(k_ws=0.5)])
+                                 dict(k_ws=0.5), dict(source_implicit=True),
+                                 dict(source_implicit=True, integrator='midpoint')])
 def test_create_rejects_bad_numerics(lib, bad):
     p = S.make_problem(system=14, dim=1, nx=16)
     n = S.make_numerics(**bad)

@@ -18,7 +18,7 @@ NUM = dict(order=2, integrator='ssprk2', flux='hll', limiter='minmod', cfl=0.5)
 
 def small_batch(seed=5, n=7):
     rng = np.random.default_rng(seed)
-    sizes = [100, 63, 64, 257, 500, 33, 1000][:n]
+    sizes = [100, 60, 61, 252, 500, 124, 1000][:n]   # tile edges: 60, 124 and 252 cells
     out = []
     for k in range(n):
         out.append(dict(n=sizes[k], p_ratio=float(rng.uniform(2, 100)), rho_ratio=float(rng.uniform(2, 20)),
@@ -63,10 +63,13 @@ def test_batch_equals_instances_run_alone_bitwise(gpu_lib, precision):
         assert np.array_equal(Ub, Us), d
 
 
-@pytest.mark.parametrize('launch', [(64, 2), (128, 4), (256, 8), (64, 16)])
+@pytest.mark.parametrize('launch', [(64, 1, 2), (64, 2, 4), (64, 4, 8), (128, 1, 4), (128, 2, 8),
+                                    (256, 1, 8), (64, 1, 16), (64, 2, 1)])
 def test_batch_launch_shapes_do_not_change_results(gpu_lib, launch):
+    """(threads, cells per thread, workgroups per CU): tiles of 60 to 252 cells, work-list
+    ranges of one to many tiles per workgroup."""
     insts = small_batch(seed=8)
-    ref, _, _ = run_batch(gpu_lib, insts, launch=(64, 4))
+    ref, _, _ = run_batch(gpu_lib, insts, launch=(64, 1, 4))
     got, _, _ = run_batch(gpu_lib, insts, launch=launch)
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
@@ -74,10 +77,11 @@ def test_batch_launch_shapes_do_not_change_results(gpu_lib, launch):
 
 def test_batch_autotune_keeps_state_and_results(gpu_lib):
     insts = small_batch(seed=9)
-    ref, _, _ = run_batch(gpu_lib, insts, launch=(64, 4))
+    ref, _, _ = run_batch(gpu_lib, insts, launch=(64, 1, 4))
     got, info, tuned = run_batch(gpu_lib, insts, autotune=True)
     print('autotuned launch', tuned, flush=True)
-    assert tuned['threads'] in (64, 128, 256) and tuned['cell_updates_per_s'] > 0
+    assert tuned['threads'] in (64, 128, 256) and tuned['cells_per_thread'] in (1, 2, 4)
+    assert tuned['threads'] * tuned['cells_per_thread'] <= 256 and tuned['cell_updates_per_s'] > 0
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
 
@@ -105,3 +109,31 @@ def test_batch_collisionless_instance_and_status(gpu_lib):
     parts, info, _ = run_batch(gpu_lib, insts)
     assert info['status'] == 'OK' and info['fail_code'] == 0
     assert all(abs(p['t'] - d['t_end']) < 1e-14 for p, d in zip(info['instances'], insts))
+
+
+@pytest.mark.parametrize('bad', [(64, 3, 4), (256, 2, 4), (128, 4, 4), (32, 1, 4), (64, 1, 0), (64, 1, 33)])
+def test_batch_rejects_unsupported_launch_shapes(gpu_lib, bad):
+    b = gpu_lib.MaxEntBatch(small_batch(n=2), **NUM)
+    try:
+        with pytest.raises(gpu_lib.MaxentError):
+            b.set_launch(*bad)
+        assert b.launch() == (64, 1, 4)   # unchanged by the rejected calls
+    finally:
+        b.close()
+
+
+def test_batch_queue_order_and_one_tile_instances(gpu_lib):
+    """Instances of one tile or less (4 to 60 cells) between long ones, given in increasing
+    order of work so that the queue reverses them: results equal each instance run alone."""
+    rng = np.random.default_rng(21)
+    sizes = [4, 7, 60, 61, 200, 700]
+    insts = [dict(n=n, p_ratio=float(rng.uniform(2, 50)), rho_ratio=float(rng.uniform(2, 10)), kn=0.01,
+                  t_end=0.004 * (k + 1)) for k, n in enumerate(sizes)]
+    for d in insts:
+        d['tau_ref'] = I.kn_to_tau_ref(d['kn'])
+    parts, info, _ = run_batch(gpu_lib, insts, launch=(128, 2, 2))
+    assert info['n_active'] == 0
+    for d, Ub, pi in zip(insts, parts, info['instances']):
+        Us, si = run_single(gpu_lib, d)
+        assert pi['steps'] == si['steps'] and pi['t'] == si['t']
+        assert np.array_equal(Ub, Us), d

@@ -87,7 +87,7 @@ def test_sod5_full_run_to_t_end(gpu_lib):
     assert np.all(d1 <= 1e-12 * b1 + ob.SPREAD_FACTOR * spread)
 
 
-@pytest.mark.parametrize('nx', [200, 63, 64, 5])
+@pytest.mark.parametrize('nx', [200, 60, 61, 121, 5])   # 60-cell tiles: one, one + 1, two + 1
 def test_sod14_muscl_rk2_one_step(gpu_lib, nx):
     compare(f'sod14 nx={nx} 1 step', gpu_lib, dict(SOD14, nx=nx), I.sod_prims(14, nx), 1,
             tau_ref=TAU_SOD)
@@ -113,7 +113,7 @@ def test_sod14_knudsen_sweep_20000_cells(gpu_lib, kn):
     Ug, info = gpu_run(gpu_lib, kw, W0, 6, dt=dt, tau_ref=tau)
     Ug = Ug[:, 0, :]
     rng = np.random.default_rng(int(kn * 1000) + 7)
-    cells = [0, 1, 62, 63, 126, 9990, 9995, 9999, 10000, 10004, 10011, 19998, 19999]
+    cells = [0, 1, 59, 60, 119, 120, 9990, 9995, 9999, 10000, 10004, 10011, 19998, 19999]
     cells += [int(c) for c in rng.integers(9970, 10030, 10)] + [int(c) for c in rng.integers(0, nx, 5)]
     vals, spread = ob.oracle_cells_1d(W0, cells, kw, 6, dt, tau)
     scale = np.maximum(np.maximum(np.abs(mo.prim_to_cons14(W0)).max(1), np.abs(vals).max(1)),
