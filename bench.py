@@ -202,6 +202,37 @@ def batch_record(stream, steps=5000, chunk=500):
     return out
 
 
+def paper_jets_record(stream, n=1200, steps=2000):
+    """The paper's own crossed jets (Section 6): 1200^2 cells, M = 5 jets of width L/7 on the
+    left and bottom walls at a right angle, background 1e-5, van Albada, HLL, forward Euler,
+    CFL 0.5, collisionless, FP64.  `steps` CFL steps from rest are timed (the jets cross the
+    middle of the domain at about 1700 steps)."""
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+    pj = inputs.PAPER_JETS
+    s = solver.MaxEntSolver(system=14, dim=2, nx=n, ny=n, order=2, integrator='fe', flux='hll',
+                            limiter='vanalbada', cfl=0.5, sigma_lim=1e-4,
+                            bc=('jet', 'transmissive', 'jet', 'transmissive'), jets=list(pj['jets']),
+                            jet_mach=pj['mach'], jet_rho=pj['rho'], jet_T=pj['T'], stream=stream)
+    s.init_state(inputs.paper_jets_initial(n, n))
+    s.step(3, check=False)
+    s.init_state(inputs.paper_jets_initial(n, n))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    info = s.step(steps, check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    s.close()
+    return {'workload': f'paper crossed jets (M 5, L/7, right angle, background 1e-5), {n}x{n}, '
+                        'van Albada + HLL + forward Euler, CFL 0.5, collisionless, FP64',
+            'steps': info['steps'], 'status': info['status'], 't': info['t'], 'ms': ms,
+            'value': n * n * info['steps'] / (ms / 1e3), 'unit': 'cell-updates/s',
+            'ms_per_step': ms / max(info['steps'], 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -216,6 +247,8 @@ def main():
                     help='skip the adjoint / forward timing of the 512^2 crossed jets')
     ap.add_argument('--no-batch', action='store_true',
                     help='skip the batched 1D shock-tube record')
+    ap.add_argument('--no-paper-jets', action='store_true',
+                    help="skip the paper's own crossed-jets geometry (1200^2, forward Euler)")
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a plain 2 GiB device copy (HBM counter calibration)')
     a = ap.parse_args()
@@ -336,6 +369,8 @@ def main():
         out['adjoint'] = adjoint_record(stream)
     if not a.no_batch:
         out['batched'] = batch_record(stream)
+    if not a.no_paper_jets:
+        out['paper_jets'] = paper_jets_record(stream)
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -1,6 +1,7 @@
 // Host tangent-linear reference for the discrete adjoint: the crossed-jets scheme (14 moments,
-// 2D, jet inflow on the left wall, transmissive elsewhere, MUSCL with the common minmod limiter
-// and positivity fallback, HLL, local-tau BGK source, SSP-RK2), written as plain loops over the
+// 2D, jet inflow on up to four walls, transmissive elsewhere, MUSCL with the common minmod or
+// van Albada limiter and positivity fallback, HLL, local-tau BGK source, SSP-RK2 or forward
+// Euler), written as plain loops over the
 // library's own templated pointwise functions and run with a dual-number scalar.  One run gives
 // the exact forward-mode derivative dJ/dp of J = sum(w * U_n) along one input direction: the jet
 // Mach number, the jet density, tau_ref, or a given direction of U_0.  With "frozen" the limiter
@@ -8,8 +9,10 @@
 // adjoint's frozen-limiter mode transposes.  Time steps are read from the input (frozen).
 //
 // Input (binary, native endianness): int32 nx, ny, nsteps, seed (0 Mach, 1 jet rho, 2 tau_ref,
-// 3 U0 direction), frozen; float64 mach, rho_j, T_j, tau_ref; nsteps float64 dt;
-// U0 [14][ny][nx]; v [14][ny][nx]; w [14][ny][nx].
+// 3 U0 direction), frozen; float64 mach, rho_j, T_j, tau_ref; int32 integrator (0 forward
+// Euler, 1 SSP-RK2), limiter (0 minmod, 1 van Albada), n_jets; n_jets x float64 (centre along
+// the wall, width, angle in degrees, wall 0 x-low / 1 x-high / 2 y-low / 3 y-high);
+// nsteps float64 dt; U0 [14][ny][nx]; v [14][ny][nx]; w [14][ny][nx].
 // Output: "J dJ" as two numbers.
 #include <cmath>
 #include <cstdio>
@@ -51,9 +54,10 @@ inline D mlog(D a) { return D(std::log(a.v), a.d / a.v); }
 using dual::D;
 using mx::Sys14;
 
-static int NX, NY;
+static int NX, NY, INTEG = 1, LIMITER = 0, NJ = 0;
 static double DX, DY;
-static const double JYC[2] = {0.35, 0.65}, JW[2] = {0.1, 0.1}, JANG[2] = {30.0, -30.0};
+static double JC[4], JW[4], JANG[4];
+static int JWALL[4];
 
 struct Scheme {
   D mach, rhoj, tau_ref;
@@ -70,11 +74,16 @@ struct Scheme {
     D Uc[14];
     for (int v = 0; v < 14; ++v) Uc[v] = A[((size_t)v * NY + sj) * NX + si];
     Sys14::cons_to_prim(Uc, W);
-    if (gi < 0) {
-      double yc = (sj + 0.5) * DY;
+    int wall = -1, s = 0;
+    if (gi < 0) { wall = 0; s = sj; }
+    else if (gi >= NX) { wall = 1; s = sj; }
+    else if (gj < 0) { wall = 2; s = si; }
+    else if (gj >= NY) { wall = 3; s = si; }
+    if (wall >= 0) {
+      double c = (wall < 2) ? (s + 0.5) * DY : (s + 0.5) * DX;
       int hit = -1;
-      for (int k = 0; k < 2; ++k)
-        if (yc >= JYC[k] - 0.5 * JW[k] && yc <= JYC[k] + 0.5 * JW[k]) hit = k;
+      for (int k = 0; k < NJ; ++k)
+        if (JWALL[k] == wall && c >= JC[k] - 0.5 * JW[k] && c <= JC[k] + 0.5 * JW[k]) hit = k;
       if (hit >= 0) {
         double a = JANG[hit] * M_PI / 180.0;
         D spd = mach * D(std::sqrt(5.0 / 3.0 * Tj));
@@ -89,7 +98,7 @@ struct Scheme {
   }
 
   D phi_of(const D* Wm, const D* Wc, const D* Wp) {
-    D phi = mx::limiter_factor<Sys14>(Wm, Wc, Wp, 0);
+    D phi = mx::limiter_factor<Sys14>(Wm, Wc, Wp, LIMITER);
     if (phi > D(0)) {
       D Wf[14];
       mx::face_state<Sys14>(Wm, Wc, Wp, phi, D(1), Wf);
@@ -155,6 +164,10 @@ struct Scheme {
     std::vector<D> L1, L2, Us(U.size());
     residual(U, L1);
     for (size_t k = 0; k < U.size(); ++k) Us[k] = U[k] + D(dt) * L1[k];
+    if (INTEG == 0) {
+      U = Us;
+      return;
+    }
     residual(Us, L2);
     for (size_t k = 0; k < U.size(); ++k) U[k] = D(0.5) * U[k] + D(0.5) * (Us[k] + D(dt) * L2[k]);
   }
@@ -167,6 +180,15 @@ int main(int argc, char** argv) {
   int hdr[5];
   double par[4];
   if (std::fread(hdr, 4, 5, f) != 5 || std::fread(par, 8, 4, f) != 4) return 2;
+  int opt[3];
+  if (std::fread(opt, 4, 3, f) != 3) return 2;
+  INTEG = opt[0]; LIMITER = opt[1]; NJ = opt[2];
+  if (NJ < 0 || NJ > 4) return 2;
+  for (int k = 0; k < NJ; ++k) {
+    double jd[4];
+    if (std::fread(jd, 8, 4, f) != 4) return 2;
+    JC[k] = jd[0]; JW[k] = jd[1]; JANG[k] = jd[2]; JWALL[k] = (int)jd[3];
+  }
   NX = hdr[0]; NY = hdr[1];
   const int nsteps = hdr[2], seed = hdr[3];
   DX = 1.0 / NX; DY = 1.0 / NY;

@@ -1,0 +1,138 @@
+"""The sigma_lim study (survey row f2): cost and accuracy of the 5-moment Sod tube as the
+limiting parameter sigma_lim varies, for several Knudsen numbers (the paper's section on the
+effect of sigma_lim and computational cost, within the Sod shock-tube study).
+
+Workload: 1000 cells, first-order HLL, forward Euler, CFL 0.5, t = 0.2, Kn in {1e-3, 1e-2,
+0.1, 1, collisionless}, sigma_lim in {1e-2, 1e-3, 1e-4, 1e-5}.  Cost is the number of CFL steps
+(implementation independent, as in the paper); the Euler equations' cost on the same grid is
+the step count that their largest characteristic speed over the exact Riemann solution
+(gamma = 3 for one velocity degree of freedom) imposes at the same CFL number.  Accuracy is the
+L1 distance of each run's density and heat flux from the sigma_lim = 1e-5 run.
+
+Checked statements of the paper, as measured here:
+  * a larger sigma_lim lowers the cost (the maximum wave speed is capped);
+  * for rarefied conditions (Kn >= 0.1) the cost hardly depends on Kn;
+  * collisions lower the cost (Kn <= 1e-2), most at Kn = 1e-3;
+  * the 5-moment system costs tens of Euler solves or more;
+  * smaller sigma_lim moves the collisionless solution less (convergence as sigma_lim -> 0).
+The table is printed (run with -s).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2401_15233_amd import inputs as I
+from kinetic_refs import exact_riemann
+import oracle_bridge as ob
+
+pytestmark = pytest.mark.gpu
+
+SOD5 = dict(system=5, dim=1, nx=1000, order=1, integrator='fe', flux='hll', cfl=0.5,
+            bc=('transmissive',) * 4)
+KNS = [1e-3, 1e-2, 0.1, 1.0, 0.0]          # 0.0: collisionless
+SIGMAS = [1e-2, 1e-3, 1e-4, 1e-5]
+T_END = 0.2
+
+
+def euler_steps(nx=1000, cfl=0.5, t_end=T_END, gamma=3.0):
+    xi = np.linspace(-5.0, 5.0, 20001)
+    rho, u, p = exact_riemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), gamma, xi)
+    smax = float(np.max(np.abs(u) + np.sqrt(gamma * p / rho)))
+    return math.ceil(t_end * smax / (cfl / nx)), smax
+
+
+@pytest.fixture(scope='module')
+def study(gpu_lib):
+    runs = {}
+    W0 = I.sod_prims(5, SOD5['nx'])
+    for sl in SIGMAS:
+        for kn in KNS:
+            s = gpu_lib.MaxEntSolver(**dict(SOD5, sigma_lim=sl))
+            s.init_state(W0)
+            tau = I.kn_to_tau_ref(kn) if kn > 0 else 0.0
+            info = {'t': 0.0}
+            while info['t'] < T_END * (1.0 - 1e-12):
+                info = s.step(5000, tau_ref=tau, t_end=T_END)
+            W = s.get('primitive').cpu().numpy()[:, 0, :]
+            s.close()
+            runs[(sl, kn)] = (info['steps'], W)
+    ne, smax = euler_steps()
+    print(f'\nEuler (gamma = 3) steps on the same grid: {ne} (largest speed {smax:.4f})')
+    print('steps (and x Euler) per sigma_lim (rows) and Kn (columns: ' +
+          ', '.join('free' if k == 0 else f'{k:g}' for k in KNS) + ')')
+    for sl in SIGMAS:
+        row = '  '.join(f'{runs[(sl, kn)][0]:7d} ({runs[(sl, kn)][0] / ne:5.1f}x)' for kn in KNS)
+        print(f'  sigma_lim {sl:7.0e}: {row}')
+    print('L1 distance from the sigma_lim = 1e-5 run, density | heat flux (relative to its L1 norm)')
+    for kn in KNS:
+        ref = runs[(1e-5, kn)][1]
+        cells = []
+        for sl in SIGMAS[:-1]:
+            W = runs[(sl, kn)][1]
+            dr = np.abs(W[0] - ref[0]).sum() / np.abs(ref[0]).sum()
+            dq = np.abs(W[3] - ref[3]).sum() / max(np.abs(ref[3]).sum(), 1e-300)
+            cells.append(f'{sl:.0e}: {dr:.2e} | {dq:.2e}')
+        print(f'  Kn {"free" if kn == 0 else f"{kn:g}":>5}:  ' + '   '.join(cells))
+    return runs, ne
+
+
+def test_cost_falls_as_sigma_lim_rises(study):
+    runs, _ = study
+    for kn in KNS:
+        steps = [runs[(sl, kn)][0] for sl in SIGMAS]
+        assert all(a <= b for a, b in zip(steps, steps[1:])), (kn, steps)
+    # in rarefied conditions the cap matters a lot
+    assert runs[(1e-5, 0.0)][0] > 5 * runs[(1e-2, 0.0)][0]
+
+
+def test_rarefied_cost_hardly_depends_on_kn(study):
+    runs, _ = study
+    for sl in SIGMAS:
+        steps = [runs[(sl, kn)][0] for kn in (0.1, 1.0, 0.0)]
+        assert max(steps) <= 1.15 * min(steps), (sl, steps)
+
+
+def test_collisions_lower_the_cost(study):
+    runs, _ = study
+    for sl in SIGMAS:
+        free = runs[(sl, 0.0)][0]
+        assert runs[(sl, 1e-2)][0] < free and runs[(sl, 1e-3)][0] < runs[(sl, 1e-2)][0]
+    assert runs[(1e-4, 1e-3)][0] < 0.25 * runs[(1e-4, 0.0)][0]
+
+
+def test_cost_against_the_euler_equations(study):
+    runs, ne = study
+    # at the default sigma_lim = 1e-4, rarefied runs take tens of Euler step counts
+    assert runs[(1e-4, 0.0)][0] > 10 * ne
+    # near the continuum the count approaches the Euler one (the 5-moment equilibrium speed,
+    # sqrt(5 + sqrt 10) c, exceeds Euler's sqrt(3) c)
+    assert runs[(1e-4, 1e-3)][0] < 5 * ne
+
+
+def test_smaller_sigma_lim_converges(study):
+    runs, _ = study
+    ref = runs[(1e-5, 0.0)][1]
+    d = [np.abs(runs[(sl, 0.0)][1][0] - ref[0]).sum() / np.abs(ref[0]).sum() for sl in SIGMAS[:-1]]
+    assert d[0] > d[1] > d[2], d
+
+
+def test_largest_sigma_lim_run_matches_oracle(gpu_lib):
+    """Parity of a study configuration away from the default sigma_lim: collisionless,
+    sigma_lim = 1e-2, to t = 0.2 (L1 against the oracle's own L1 spread, as for the default
+    Sod run)."""
+    kw = dict(SOD5, sigma_lim=1e-2)
+    W0 = I.sod_prims(5, 1000)
+    s = gpu_lib.MaxEntSolver(**kw)
+    s.init_state(W0)
+    info = s.step(20000, tau_ref=0.0, t_end=T_END)
+    Ug = s.get('conserved').cpu().numpy()[:, 0, :]
+    s.close()
+    base, spread, t, n, nspread = ob.oracle_with_l1_spread(kw, W0, T_END, 0.0)
+    d1 = np.abs(Ug - base).sum(1)
+    b1 = np.abs(base).sum(1)
+    print(f'sigma_lim 1e-2 collisionless: L1 relative error {np.array2string(d1 / b1, precision=2)}, '
+          f'oracle L1 spread {np.array2string(spread / b1, precision=2)}; steps gpu {info["steps"]} '
+          f'oracle {n} (spread {nspread})', flush=True)
+    assert np.all(d1 <= 1e-12 * b1 + ob.SPREAD_FACTOR * spread)
+    assert abs(info['steps'] - n) <= ob.SPREAD_FACTOR * nspread + 2
