@@ -11,6 +11,11 @@ The workload: unit square, two Maxwellian jets (width 0.1, centred at y = 0.35 a
 rho = 1e-3, T = 1; transmissive elsewhere; Kn = 0.1 through a local BGK collision time;
 MUSCL-minmod, HLL, SSP-RK2, CFL 0.4, sigma_lim = 1e-4.  Inputs are synthetic (the problem
 definition itself; no dataset).
+
+Sub-records beside the headline FP64 value: the same workload in mixed precision; the
+discrete adjoint of the 512^2 jets against its forward run; 512 batched 1D shock tubes (mixed
+and FP64, autotuned launch shape); the paper's own crossed-jets geometry at 1200^2 (forward
+Euler, van Albada); and the CPU oracle on a bounded sample (skip each with its --no-* flag).
 """
 import argparse
 import json

@@ -73,13 +73,14 @@ __device__ __forceinline__ void load_prims(const StageParams& p, const double* U
       if (SYS::odd(v, 1)) W[v] = -W[v];
   }
   if constexpr (NV == 14) {
-    if (p.n_jets > 0) {
-      int k = -1;
-      if (gi < 0 && p.bc[0] == 3) k = jet_on_wall(p, 0, sj);
-      else if (gi >= p.nx && p.bc[1] == 3) k = jet_on_wall(p, 1, sj);
-      else if (gj < 0 && p.bc[2] == 3) k = jet_on_wall(p, 2, si);
-      else if (gj >= p.ny && p.bc[3] == 3) k = jet_on_wall(p, 3, si);
-      if (k >= 0) jet_state(p, k, W);
+    // ghost cells only (one unsigned compare per axis catches both sides)
+    if (p.n_jets > 0 && ((unsigned)gi >= (unsigned)p.nx || (unsigned)gj >= (unsigned)p.ny)) {
+      const int wall = gi < 0 ? 0 : (gi >= p.nx ? 1 : (gj < 0 ? 2 : 3));
+      const int kind = wall == 0 ? p.bc[0] : (wall == 1 ? p.bc[1] : (wall == 2 ? p.bc[2] : p.bc[3]));
+      if (kind == 3) {
+        const int k = jet_on_wall(p, wall, wall < 2 ? sj : si);
+        if (k >= 0) jet_state(p, k, W);
+      }
     }
   }
 }

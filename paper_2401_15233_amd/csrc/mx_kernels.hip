@@ -200,8 +200,8 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + off];
       SYS::cons_to_prim(Ub, W);
       double Cs[NV];
-      const bool explicit_src = p.use_source && !p.src_implicit;
-      if (explicit_src) {
+      const bool implicit_src = p.use_source && p.src_implicit;
+      if (p.use_source && !implicit_src) {
         double rho = W[0];
         double T = SYS::pressure(W) / rho;
         double tau = (p.tau_mode == 0) ? p.tau_ref * (p.rho_ref / rho) * sqrt(p.T_ref / T) : p.tau_ref;
@@ -222,8 +222,9 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         else if (p.mode == MODE_HEUN2) o = 0.5 * p.Ua[v * p.plane + off] + 0.5 * (Ub[v] + dt * L);
         else o = p.Ua[v * p.plane + off] + dt * L;
         Un[v] = o;
+        if (!implicit_src) p.Uout[v * p.plane + off] = o;
       }
-      if (p.use_source && p.src_implicit) {
+      if (implicit_src) {
         // backward-Euler BGK relaxation of the transported state (forward-Euler stages only):
         // the source keeps rho, rho u and the energy, so the Maxwellian and tau of the new
         // state are those of the transported state, and U_new = (U_t + h U_eq) / (1 + h),
@@ -238,10 +239,11 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         SYS::equilibrium(Wt, We);
         SYS::prim_to_cons(We, Ue);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Un[v] = (Un[v] + h * Ue[v]) * w;
+        for (int v = 0; v < NV; ++v) {
+          Un[v] = (Un[v] + h * Ue[v]) * w;
+          p.Uout[v * p.plane + off] = Un[v];
+        }
       }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) p.Uout[v * p.plane + off] = Un[v];
       bool fin = true;
 #pragma unroll
       for (int v = 0; v < NV; ++v) fin = fin && isfinite(Un[v]);

