@@ -207,6 +207,44 @@ def batch_record(stream, steps=5000, chunk=500):
     return out
 
 
+def batch_full_record(stream, precision='fp64', chunk=400):
+    """The batched workload run to completion (every tube to t = 0.15): makespan, total
+    cell-updates and the balance efficiency = (full-run rate) / (rate with every tube active,
+    from the autotuner's trial), i.e. how much the shrinking active set and the longest tube's
+    step latency cost.  About two minutes; progress goes to stderr."""
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+    insts = inputs.batch_instances()
+    for d in insts:
+        d['tau_ref'] = inputs.kn_to_tau_ref(d['kn'])
+        d['t_end'] = 0.15
+    b = solver.MaxEntBatch(insts, stream=stream, precision=precision, order=2, integrator='ssprk2',
+                           cfl=0.5, k_ws=1.2)
+    b.init_state(inputs.batch_sod_prims(insts))
+    tuned = b.autotune(trial_steps=20)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    info = None
+    for _ in range(1000):
+        info = b.step(max_steps=10000, chunk=chunk, check=False)
+        print(f'batch {precision}: longest {info["max_steps"]} steps, {info["n_active"]} active, '
+              f'{time.time() - t0:.1f} s', file=sys.stderr, flush=True)
+        if info['n_active'] == 0 or info['fail_code']:
+            break
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    b.close()
+    steps = sorted(p['steps'] for p in info['instances'])
+    q = lambda f: steps[int(f * (len(steps) - 1))]  # noqa: E731
+    rate = info['cell_updates'] / wall
+    return {'precision': precision, 'makespan_s': wall, 'cell_updates': info['cell_updates'],
+            'value': rate, 'unit': 'cell-updates/s', 'failed': int(info['fail_code'] != 0),
+            'launch': {k: tuned[k] for k in ('threads', 'cells_per_thread', 'wg_per_cu')},
+            'all_active_rate': tuned['cell_updates_per_s'],
+            'balance_efficiency': rate / tuned['cell_updates_per_s'],
+            'steps_min_median_p90_p99_max': [q(0), q(0.5), q(0.9), q(0.99), q(1.0)]}
+
+
 def paper_jets_record(stream, n=1200, steps=2000):
     """The paper's own crossed jets (Section 6): 1200^2 cells, M = 5 jets of width L/7 on the
     left and bottom walls at a right angle, background 1e-5, van Albada, HLL, forward Euler,
@@ -252,6 +290,8 @@ def main():
                     help='skip the adjoint / forward timing of the 512^2 crossed jets')
     ap.add_argument('--no-batch', action='store_true',
                     help='skip the batched 1D shock-tube record')
+    ap.add_argument('--batch-full', action='store_true',
+                    help='only run the batched tubes to completion (FP64 and mixed; ~4 minutes)')
     ap.add_argument('--no-paper-jets', action='store_true',
                     help="skip the paper's own crossed-jets geometry (1200^2, forward Euler)")
     ap.add_argument('--copy-calibration', action='store_true',
@@ -268,6 +308,11 @@ def main():
     from paper_2401_15233_amd import solver, inputs
 
     torch.cuda.set_device(0)
+    if a.batch_full:
+        stream = torch.cuda.current_stream()
+        print(json.dumps({'batched_full_run': [batch_full_record(stream, p) for p in ('fp64', 'mixed')]}),
+              flush=True)
+        return
     if a.copy_calibration:
         m = 256 * 1024 * 1024
         src = torch.ones(m, dtype=torch.float64, device='cuda')

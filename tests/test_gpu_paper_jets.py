@@ -1,5 +1,5 @@
 """The paper's own crossed-jets geometry and the point-implicit BGK source, GPU against the
-oracle (survey row f4).
+oracle.
 
 * Geometry (Section 6): unit square, M = 5 jets of width L/7 centred on the left and bottom
   walls and pointing to the centre (at a right angle), background at 1e-5 of the jet density,

@@ -1,4 +1,4 @@
-"""The sigma_lim study (survey row f2): cost and accuracy of the 5-moment Sod tube as the
+"""The sigma_lim study: cost and accuracy of the 5-moment Sod tube as the
 limiting parameter sigma_lim varies, for several Knudsen numbers (the paper's section on the
 effect of sigma_lim and computational cost, within the Sod shock-tube study).
 
