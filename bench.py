@@ -245,6 +245,69 @@ def batch_full_record(stream, precision='fp64', chunk=400):
             'steps_min_median_p90_p99_max': [q(0), q(0.5), q(0.9), q(0.99), q(1.0)]}
 
 
+def _run_to(s, t_end, tau_ref, chunk=5000):
+    info = {'t': 0.0}
+    while info['t'] < t_end * (1.0 - 1e-12):
+        info = s.step(chunk, tau_ref=tau_ref, t_end=t_end, check=False)
+        if info['status'] != 'OK':
+            break
+    return info
+
+
+def sod_records(stream):
+    """The two Sod workloads.  At these sizes a step is bound by launch latency and the
+    length of one tile's work, not by throughput, so time per step is the figure:
+    (a) 5-moment, 1000 cells, first-order HLL, forward Euler, CFL 0.5, Kn = 0.01, to t = 0.2;
+    (b) 14-moment, 20000 cells, MUSCL-minmod + HLL + SSP-RK2, CFL 0.5, Kn in {1e-3, 1e-2, 0.1,
+    1, 10}, to t = 0.2: each Knudsen number run alone, and the five as one batch."""
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+    out = {}
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    s = solver.MaxEntSolver(system=5, dim=1, nx=1000, order=1, integrator='fe', flux='hll', cfl=0.5,
+                            stream=stream)
+    s.init_state(inputs.sod_prims(5, 1000))
+    info, ms = timed(lambda: _run_to(s, 0.2, inputs.kn_to_tau_ref(0.01)))
+    s.close()
+    out['sod5_1000_kn0.01'] = {'steps': info['steps'], 'ms': ms, 'us_per_step': 1e3 * ms / info['steps'],
+                               'status': info['status']}
+    kns = [1e-3, 1e-2, 0.1, 1.0, 10.0]
+    num = dict(order=2, integrator='ssprk2', flux='hll', limiter='minmod', cfl=0.5)
+    alone = []
+    for kn in kns:
+        s = solver.MaxEntSolver(system=14, dim=1, nx=20000, stream=stream, **num)
+        s.init_state(inputs.sod_prims(14, 20000))
+        info, ms = timed(lambda: _run_to(s, 0.2, inputs.kn_to_tau_ref(kn)))
+        s.close()
+        alone.append({'kn': kn, 'steps': info['steps'], 'ms': ms, 'us_per_step': 1e3 * ms / info['steps'],
+                      'status': info['status']})
+    out['sod14_20000_alone'] = alone
+    insts = [dict(n=20000, t_end=0.2, tau_ref=inputs.kn_to_tau_ref(kn), rho_ratio=8.0, p_ratio=10.0)
+             for kn in kns]
+    b = solver.MaxEntBatch(insts, stream=stream, **num)
+    b.init_state(inputs.batch_sod_prims(insts))
+    tuned = b.autotune(trial_steps=10)
+    b.init_state(inputs.batch_sod_prims(insts))
+    info, ms = timed(lambda: b.step(max_steps=10 ** 7, chunk=500, check=False))
+    b.close()
+    out['sod14_20000_batch_of_5'] = {'longest_steps': info['max_steps'], 'ms': ms,
+                                     'us_per_step': 1e3 * ms / info['max_steps'],
+                                     'sum_alone_ms': sum(r['ms'] for r in alone),
+                                     'launch': {k: tuned[k] for k in ('threads', 'cells_per_thread', 'wg_per_cu')},
+                                     'status': info['status']}
+    return out
+
+
 def paper_jets_record(stream, n=1200, steps=2000):
     """The paper's own crossed jets (Section 6): 1200^2 cells, M = 5 jets of width L/7 on the
     left and bottom walls at a right angle, background 1e-5, van Albada, HLL, forward Euler,
@@ -290,6 +353,8 @@ def main():
                     help='skip the adjoint / forward timing of the 512^2 crossed jets')
     ap.add_argument('--no-batch', action='store_true',
                     help='skip the batched 1D shock-tube record')
+    ap.add_argument('--sod', action='store_true',
+                    help='only time the two Sod workloads (time per step; about half a minute)')
     ap.add_argument('--batch-full', action='store_true',
                     help='only run the batched tubes to completion (FP64 and mixed; ~4 minutes)')
     ap.add_argument('--no-paper-jets', action='store_true',
@@ -308,6 +373,9 @@ def main():
     from paper_2401_15233_amd import solver, inputs
 
     torch.cuda.set_device(0)
+    if a.sod:
+        print(json.dumps({'sod': sod_records(torch.cuda.current_stream())}), flush=True)
+        return
     if a.batch_full:
         stream = torch.cuda.current_stream()
         print(json.dumps({'batched_full_run': [batch_full_record(stream, p) for p in ('fp64', 'mixed')]}),
