@@ -97,6 +97,10 @@ static std::string g_create_err;
 
 static int fail(maxent_solver* s, int code, const std::string& msg) {
   if (s) s->err = msg; else g_create_err = msg;
+  // a failed runtime call (e.g. an allocation beyond the card's memory) leaves its error as the
+  // runtime's last error, which the next launch check would report: the error is reported
+  // here, so clear it
+  if (code == MAXENT_E_NOMEM || code == MAXENT_E_DEVICE) (void)hipGetLastError();
   return code;
 }
 
