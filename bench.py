@@ -44,6 +44,7 @@ SOURCES_FOR_TRAFFIC = ('paper_2401_15233_amd/csrc/mx_kernels.hip',
                        'paper_2401_15233_amd/csrc/mx_bc.hpp',
                        'paper_2401_15233_amd/csrc/mx_internal.hpp')
 TRAFFIC_PROFILE = 'profiles/stage_kernel_jets2048_fp64_hbm_traffic.txt'
+VALU_PROFILE = 'profiles/stage_kernel_jets2048_fp64_valu.txt'
 
 
 def kernel_source_hash():
@@ -69,6 +70,22 @@ def measured_traffic():
     if kv.get('kernel_source_hash') != kernel_source_hash():
         return None
     return float(kv['hbm_bytes_per_launch'])
+
+
+def measured_valu_busy():
+    """Fraction of cycles the VALU was busy in the FP64 stage kernel, from the committed
+    rocprofv3 SQ_ACTIVE_INST_VALU / GRBM_GUI_ACTIVE summary, or None when the kernel sources
+    changed since."""
+    path = os.path.join(ROOT, VALU_PROFILE)
+    if not os.path.exists(path):
+        return None
+    busy, h = None, None
+    for line in open(path):
+        if line.startswith('valu_busy_percent'):
+            busy = float(line.rsplit(':', 1)[1]) / 100.0
+        elif line.startswith('kernel_source_hash:'):
+            h = line.split(':', 1)[1].strip()
+    return busy if h == kernel_source_hash() else None
 
 
 def jets_kwargs(n, k_ws=1.2):
@@ -449,6 +466,7 @@ def main():
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VECTOR_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VECTOR_PEAK_TFLOPS,
                      'traffic': measured_traffic(),
+                     'valu_busy': measured_valu_busy(),
                      'kernel': f'stage_kernel<Sys14,2,2,{0 if head == "fp64" else 1},16,15,256> ({head})',
                      'avg_launch_ms': avg_stage_ms, 'launches': launches,
                      'flops_per_launch': flops_per_launch,
