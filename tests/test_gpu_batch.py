@@ -137,3 +137,48 @@ def test_batch_queue_order_and_one_tile_instances(gpu_lib):
         Us, si = run_single(gpu_lib, d)
         assert pi['steps'] == si['steps'] and pi['t'] == si['t']
         assert np.array_equal(Ub, Us), d
+
+
+@pytest.mark.parametrize('precision', ['fp64', 'mixed'])
+def test_full_size_batch_sampled_tubes(gpu_lib, precision):
+    """The batched workload at full size in the benchmark's launch configuration (512 tubes,
+    4.29 M cells, autotuned shape, wave speeds x 1.2): after 300 steps of the whole batch,
+    sampled tubes (the smallest, the largest, the strongest pressure ratio, a seeded one) equal
+    the same tubes run alone bit for bit, and the smallest one matches the oracle."""
+    insts = I.batch_instances()
+    for d in insts:
+        d['tau_ref'] = I.kn_to_tau_ref(d['kn'])
+        d['t_end'] = 0.15
+    num = dict(order=2, integrator='ssprk2', flux='hll', limiter='minmod', cfl=0.5, k_ws=1.2)
+    b = gpu_lib.MaxEntBatch(insts, precision=precision, **num)
+    b.init_state(I.batch_sod_prims(insts))
+    tuned = b.autotune(trial_steps=3)
+    b.init_state(I.batch_sod_prims(insts))
+    info = b.step(max_steps=300, chunk=100)
+    parts = b.split(b.get('conserved').cpu().numpy())
+    b.close()
+    print(f'{precision}: launch {tuned}, longest {info["max_steps"]} steps', flush=True)
+    sizes = [d['n'] for d in insts]
+    picks = {int(np.argmin(sizes)), int(np.argmax(sizes)),
+             int(np.argmax([d['p_ratio'] for d in insts])), int(np.random.default_rng(4).integers(512))}
+    for k in sorted(picks):
+        d = insts[k]
+        steps = info['instances'][k]['steps']
+        s = gpu_lib.MaxEntSolver(system=14, dim=1, nx=d['n'], precision=precision, **num)
+        s.init_state(I.batch_sod_prims([d]))
+        si = s.step(steps, tau_ref=d['tau_ref'], t_end=d['t_end'])
+        Us = s.get('conserved').cpu().numpy()[:, 0, :]
+        s.close()
+        assert si['steps'] == steps and si['t'] == info['instances'][k]['t']
+        assert np.array_equal(parts[k], Us), (k, d['n'])
+    if precision == 'fp64':
+        k = int(np.argmin(sizes))
+        d = insts[k]
+        kw = dict(system=14, dim=1, nx=d['n'], bc=('transmissive',) * 4, **num)
+        steps = info['instances'][k]['steps']
+        base, spread, t, n = ob.oracle_with_spread(kw, I.batch_sod_prims([d]), nsteps=steps,
+                                                    tau_ref=d['tau_ref'], t_end=d['t_end'])
+        ok, ratio, err = ob.within_spread(parts[k], base, spread)
+        print(f'smallest tube ({d["n"]} cells, {steps} steps) vs oracle: error {err.max():.2e}, '
+              f'bound use {ratio:.2f}', flush=True)
+        assert ok and n == steps
