@@ -176,9 +176,15 @@ def test_full_size_batch_sampled_tubes(gpu_lib, precision):
         d = insts[k]
         kw = dict(system=14, dim=1, nx=d['n'], bc=('transmissive',) * 4, **num)
         steps = info['instances'][k]['steps']
-        base, spread, t, n = ob.oracle_with_spread(kw, I.batch_sod_prims([d]), nsteps=steps,
-                                                    tau_ref=d['tau_ref'], t_end=d['t_end'])
-        ok, ratio, err = ob.within_spread(parts[k], base, spread)
-        print(f'smallest tube ({d["n"]} cells, {steps} steps) vs oracle: error {err.max():.2e}, '
-              f'bound use {ratio:.2f}', flush=True)
-        assert ok and n == steps
+        # 300 steps through a shock with minmod: a +-4 ulp input change already moves single
+        # cells by ~1e-2 of the field (limiter branches flip), so the oracle's own pointwise
+        # spread is not a stable bar here; the L1 norm per moment is, as for the other long runs
+        base, spread, t, n, nspread = ob.oracle_with_l1_spread(kw, I.batch_sod_prims([d]), d['t_end'],
+                                                               d['tau_ref'], nsteps=steps)
+        d1 = np.abs(parts[k] - base).sum(1)
+        b1 = np.maximum(np.abs(base).sum(1), 1e-300)
+        print(f'smallest tube ({d["n"]} cells, {steps} steps) vs oracle: L1 relative error '
+              f'{np.array2string(d1 / b1, precision=1)}, oracle L1 spread '
+              f'{np.array2string(spread / b1, precision=1)}', flush=True)
+        assert np.all(d1 <= 1e-12 * b1 + ob.SPREAD_FACTOR * spread)
+        assert n == steps and abs(t - info['instances'][k]['t']) <= 1e-9 * t
