@@ -206,7 +206,8 @@ int maxent_create_batch(const maxent_problem* common, const maxent_numerics* num
                         int n_inst, const maxent_instance* instances, void* stream,
                         maxent_solver** out);
 
-/* Advance every instance until it reaches its t_end, or at most about max_steps steps.
+/* Advance every instance until it reaches its t_end, or for at most max_steps steps rounded
+ * up to whole chunks (ceil(max_steps / chunk) * chunk).
  * The instances form a queue ordered by estimated work (cells x steps to t_end from the
  * CFL rate of the state given to init_state, largest first; ties by index).  Each step
  * compacts the instances that still advance, in queue order, into a list of tiles that the
@@ -227,7 +228,10 @@ int maxent_get_batch_launch(maxent_solver* s, int* threads, int* cells_per_threa
 
 /* Autotuner: time trial_steps steps of each launch shape (threads x cells per thread in
  * 64x1, 64x2, 64x4, 128x1, 128x2, 256x1, times workgroups per CU 2/4/8/16) from the current
- * state, restoring the state after every trial, and keep the fastest.  Outputs may be NULL. */
+ * state, restoring the state after every trial, and keep the fastest.  Outputs may be NULL.
+ * Errors: STATE before init_state, INVAL for trial_steps outside 1..10000, NOMEM for the
+ * snapshot of the state, DEVICE if a trial fails (the launch shape is then the one before the
+ * call, and the state should be loaded again with init_state). */
 int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* threads, int* cells_per_thread,
                           int* wg_per_cu, double* best_cell_updates_per_s);
 

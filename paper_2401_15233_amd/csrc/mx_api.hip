@@ -188,7 +188,7 @@ static void free_tape(maxent_solver* s) {
 extern "C" void maxent_destroy(maxent_solver* s) {
   if (!s) return;
   free_tape(s);
-  if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->stream);
   if (s->U) (void)hipFree(s->U);
   if (s->Us) (void)hipFree(s->Us);
   if (s->stage) (void)hipFree(s->stage);
@@ -287,7 +287,12 @@ static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::S
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
-    s->ev.push_back(e);
+    try {
+      s->ev.push_back(e);
+    } catch (const std::bad_alloc&) {
+      (void)hipEventDestroy(e);
+      return hipErrorOutOfMemory;
+    }
   }
   hipError_t r = hipEventRecord(s->ev[s->ev_used], s->stream);
   if (r == hipSuccess) r = mx::launch_stage(sys, dim, ord, prec, p, s->stream);
@@ -372,7 +377,12 @@ static int batch_reset(maxent_solver* s) {
   HIP_TRY(s, hipMemcpyAsync(b->h_inst, b->d_inst, b->n_inst * sizeof(mx::BatchInst), hipMemcpyDeviceToHost,
                             s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
-  std::vector<double> work(b->n_inst);
+  std::vector<double> work;
+  try {
+    work.resize(b->n_inst);
+  } catch (const std::bad_alloc&) {
+    return fail(s, MAXENT_E_NOMEM, "host allocation failed");
+  }
   for (int i = 0; i < b->n_inst; ++i) {
     const mx::BatchInst& r = b->h_inst[i];
     double rate = __builtin_bit_cast(double, r.maxrate);
@@ -532,7 +542,13 @@ extern "C" int maxent_record(maxent_solver* s, int checkpoint_every, int max_ste
   t->max_steps = max_steps;
   const size_t field = (size_t)s->nv * s->plane * sizeof(double);
   const int n_ck = max_steps / checkpoint_every + 1;
-  t->ckpt.assign(n_ck, nullptr);
+  try {
+    t->ckpt.assign(n_ck, nullptr);
+    t->tau.reserve(max_steps);   // maxent_step appends one entry per step, up to max_steps
+  } catch (const std::bad_alloc&) {
+    free_tape(s);
+    return fail(s, MAXENT_E_NOMEM, "host allocation failed");
+  }
   hipError_t e = hipMalloc(&t->d_dt, (size_t)max_steps * sizeof(double));
   for (int k = 0; k < n_ck && e == hipSuccess; ++k) e = hipMalloc(&t->ckpt[k], field);
   if (e == hipSuccess) e = hipMemcpyAsync(t->ckpt[0], s->U, field, hipMemcpyDeviceToDevice, s->stream);
@@ -585,7 +601,11 @@ static hipError_t adjoint_workspace(maxent_solver* s) {
   const long long eplane = (long long)(nx + 4) * (dim == 2 ? ny + 4 : 1);
   const int nb = mx::adjoint_update_blocks(nx, ny);
   hipError_t e = hipSuccess;
-  t->seg.assign(2 * t->K, nullptr);
+  try {
+    t->seg.assign(2 * t->K, nullptr);
+  } catch (const std::bad_alloc&) {
+    return hipErrorOutOfMemory;
+  }
   for (auto& p : t->seg)
     if (e == hipSuccess) e = hipMalloc(&p, field);
   for (auto& p : t->lam)
@@ -634,7 +654,16 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   const int nx = s->prob.nx, ny = s->prob.ny, dim = s->prob.dim, ord = s->num.order;
   const int integ = s->num.integrator;
   const long long n = t->n;
-  std::vector<double> dts((size_t)n);
+  const long long K = t->K;
+  std::vector<double> dts;
+  std::vector<const double*> segU, segS;
+  try {
+    dts.resize((size_t)n);
+    segU.resize((size_t)K + 1);
+    segS.resize((size_t)K);
+  } catch (const std::bad_alloc&) {
+    return fail(s, MAXENT_E_NOMEM, "host allocation failed");
+  }
   if (n > 0) {
     HIP_TRY(s, hipMemcpyAsync(dts.data(), t->d_dt, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
                               s->stream));
@@ -672,9 +701,7 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   a.grad = t->grad;
   const double cdt1 = (integ == MAXENT_MIDPOINT) ? 0.5 : 1.0;
 
-  const long long K = t->K;
   const long long nseg = (n + K - 1) / K;
-  std::vector<const double*> segU((size_t)K + 1), segS((size_t)K);
   for (long long sg = nseg - 1; sg >= 0; --sg) {
     const long long k0 = sg * K, k1 = std::min(n, k0 + K);
     const int m = (int)(k1 - k0);
@@ -814,8 +841,15 @@ extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_nu
   s->batch = b;
   b->n_inst = n_inst;
   b->total = total;
-  b->init.resize(n_inst);
-  std::vector<int> cell_inst(total);
+  std::vector<int> cell_inst;
+  try {
+    b->init.resize(n_inst);
+    b->order.resize(n_inst);
+    cell_inst.resize(total);
+  } catch (const std::bad_alloc&) {
+    maxent_destroy(s);
+    return fail(nullptr, MAXENT_E_NOMEM, "host allocation failed");
+  }
   long long off = 0;
   for (int i = 0; i < n_inst; ++i) {
     mx::BatchInst r;
@@ -840,7 +874,6 @@ extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_nu
   if (e == hipSuccess) e = hipHostMalloc(&b->h_ctrl, sizeof(mx::BatchCtrl));
   if (e == hipSuccess) e = hipMalloc(&b->d_cell_inst, total * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(b->d_cell_inst, cell_inst.data(), total * sizeof(int), hipMemcpyHostToDevice);
-  b->order.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) b->order[i] = i;
   if (e == hipSuccess) e = hipMalloc(&b->d_order, n_inst * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(b->d_order, b->order.data(), n_inst * sizeof(int), hipMemcpyHostToDevice);
@@ -997,16 +1030,21 @@ extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* thr
   size_t recs = b->n_inst * sizeof(mx::BatchInst);
   double* saveU = nullptr;
   mx::BatchInst* saveI = nullptr;
-  HIP_TRY(s, hipMalloc(&saveU, field));
-  hipError_t e = hipMalloc(&saveI, recs);
-  if (e != hipSuccess) { (void)hipFree(saveU); return fail(s, MAXENT_E_NOMEM, "autotune snapshot"); }
+  hipError_t e = hipMalloc(&saveU, field);
+  if (e == hipSuccess) e = hipMalloc(&saveI, recs);
+  if (e != hipSuccess) {
+    if (saveU) (void)hipFree(saveU);
+    return fail(s, e == hipErrorOutOfMemory ? MAXENT_E_NOMEM : MAXENT_E_DEVICE,
+                std::string("autotune snapshot: ") + hipGetErrorString(e));
+  }
   e = hipMemcpyAsync(saveU, s->U, field, hipMemcpyDeviceToDevice, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(saveI, b->d_inst, recs, hipMemcpyDeviceToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   const int shapes[6][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
   const int wgs[4] = {2, 4, 8, 16};
   double best = -1.0;
-  int bt = b->nt, bc = b->cpt, bw = b->wg_per_cu;
+  const int nt0 = b->nt, cpt0 = b->cpt, wg0 = b->wg_per_cu;
+  int bt = nt0, bc = cpt0, bw = wg0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1039,7 +1077,14 @@ extern "C" int maxent_autotune_batch(maxent_solver* s, int trial_steps, int* thr
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(saveU);
   (void)hipFree(saveI);
-  if (e != hipSuccess) return fail(s, MAXENT_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    // keep the launch shape the solver had before the call
+    b->nt = nt0;
+    b->cpt = cpt0;
+    b->wg_per_cu = wg0;
+    b->graph_valid = false;
+    return fail(s, MAXENT_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  }
   b->nt = bt;
   b->cpt = bc;
   b->wg_per_cu = bw;
