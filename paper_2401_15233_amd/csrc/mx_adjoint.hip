@@ -8,13 +8,14 @@
 //   0. prep (adj_prim_kernel, adj_limiter_kernel): primitives of every cell of the domain
 //      and its two ghost layers, and each cell's common limiter factor and the variable that
 //      selected it, per direction (the forward stage's values, bit for bit);
-//   1. faces, per direction: (a) adj_face_a_kernel rebuilds the two face states of every
-//      face, evaluates their closure, wave speeds, fluxes and conserved states, takes the
-//      flux adjoint Fb = (mu_right - mu_left) / dx from the two adjacent cells
-//      (mu = mu_coef dt lam_out, zero in ghost cells) and reverses the HLL / Rusanov
-//      combination (branch replayed), writing a record per face side; (b) adj_face_b_kernel
-//      reverses closure, wave speeds, physical flux and conserved map of one face side per
-//      thread (split from (a) to keep each thread's live state in registers);
+//   1. faces, per direction (adj_face_kernel, two threads per face, one per face state):
+//      each thread takes the flux adjoint Fb = (mu_right - mu_left) / dx from the two
+//      adjacent cells (mu = mu_coef dt lam_out, zero in ghost cells), rebuilds its face state
+//      and evaluates its closure, wave speeds, flux and conserved state; the two threads
+//      exchange their wave speeds and the products Fb . F, Fb . U (lane shuffles), which is
+//      all the reverse of the HLL / Rusanov combination (branch replayed) needs besides the
+//      thread's own side; then each thread reverses closure, wave speeds, physical flux and
+//      conserved map of its own face state;
 //   2. extended cells (adj_cell_kernel): for every cell of the domain and its two ghost
 //      layers, gather the reverse of the limited reconstruction of the up to three stencil
 //      cells whose face states it feeds (limiter argmin, regime and fallback replayed);
@@ -112,28 +113,27 @@ __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
 }
 
 // ------------------------------------------------------------------ 1. faces
-// side record layout: [0,14) W, [14,28) U-bar, [28,42) F-bar, 42 lambda_min-bar,
-// 43 lambda_max-bar; record r of face fo: left side r = fo, right side r = nf + fo
 template <int D, int DIM, int ORDER>
-__global__ __launch_bounds__(ADJ_NT) void adj_face_a_kernel(AdjParams a) {
+__global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
+  // lanes 2k and 2k+1 own the left and the right state of face k; the grid has two threads
+  // per face, so both lanes of a pair pass or fail every face-uniform test together
   const StageParams& p = a.sp;
   const int n = (D == 0) ? p.nx : p.ny;           // cells along D
   const int m = (D == 0) ? p.ny : p.nx;           // lines
   const long long nf = (long long)(n + 1) * m;
-  const long long f = xcd_block() * ADJ_NT + threadIdx.x;
+  const long long f = (xcd_block() * ADJ_NT + threadIdx.x) >> 1;
+  const bool right = (threadIdx.x & 1) != 0;
   if (f >= nf) return;
   int fc, l;                                       // face fc lies between cells fc-1 and fc
   if (D == 0) { fc = (int)(f % (n + 1)); l = (int)(f / (n + 1)); }
   else { fc = (int)(f / m); l = (int)(f % m); }
   const double inv_h = (D == 0) ? p.inv_dx : p.inv_dy;
   const double mc = a.mu_coef * a.dt;
-  const long long fo = (D == 0) ? (long long)l * (n + 1) + fc : (long long)fc * m + l;
-  double* rl = a.side + fo;
-  double* rr = a.side + nf + fo;
-  const long long ns = a.nside;
+  // face-state adjoints: [0,14) of the face's left state, [14,28) of its right state
+  double* out = ((D == 0) ? a.fbx : a.fby) + (right ? 14 * nf : 0) + f;
 
   // flux adjoint from the two adjacent interior cells
-  double Fb[14];
+  double Fhb[14];
   bool any = false;
   {
     long long cl = (D == 0) ? ucell(p, fc - 1, l) : ucell(p, l, fc - 1);
@@ -143,83 +143,54 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_a_kernel(AdjParams a) {
     for (int v = 0; v < 14; ++v) {
       double ml = hl ? mc * a.lam_out[v * p.plane + cl] : 0.0;
       double mr = hr ? mc * a.lam_out[v * p.plane + cr] : 0.0;
-      Fb[v] = (mr - ml) * inv_h;
-      any = any || (Fb[v] != 0.0);
+      Fhb[v] = (mr - ml) * inv_h;
+      any = any || (Fhb[v] != 0.0);
     }
   }
   if (!any) {
 #pragma unroll
-    for (int k = 14; k < 44; ++k) { rl[k * ns] = 0.0; rr[k * ns] = 0.0; }
+    for (int v = 0; v < 14; ++v) out[v * nf] = 0.0;
     return;
   }
-  double WL[14], WR[14];
+  // this lane's face state: the left state is the upper face state of cell fc-1, the right
+  // state the lower face state of cell fc
+  const int cc = right ? fc : fc - 1;
+  double W[14];
   if constexpr (ORDER == 2) {
-    double A[14], B[14], C[14], E[14];
-    const long long eB = ext_idx<D, DIM>(a, fc - 1, l), eC = ext_idx<D, DIM>(a, fc, l);
+    const long long ec = ext_idx<D, DIM>(a, cc, l);
     const long long st = (D == 0) ? 1 : a.epitch;
-    get_w(a, eB - st, A);
-    get_w(a, eB, B);
-    get_w(a, eC, C);
-    get_w(a, eC + st, E);
-    const double phL = (D == 0) ? a.phix[eB] : a.phiy[eB];
-    const double phR = (D == 0) ? a.phix[eC] : a.phiy[eC];
-    face_state<Sys14>(A, B, C, phL, 1.0, WL);
-    face_state<Sys14>(B, C, E, phR, -1.0, WR);
+    double Sm[14], Sc[14], Sp[14];
+    get_w(a, ec - st, Sm);
+    get_w(a, ec, Sc);
+    get_w(a, ec + st, Sp);
+    const double ph = (D == 0) ? a.phix[ec] : a.phiy[ec];
+    face_state<Sys14>(Sm, Sc, Sp, ph, right ? -1.0 : 1.0, W);
   } else {
-    get_w(a, ext_idx<D, DIM>(a, fc - 1, l), WL);
-    get_w(a, ext_idx<D, DIM>(a, fc, l), WR);
+    get_w(a, ext_idx<D, DIM>(a, cc, l), W);
   }
-  double UL[14], FL[14], UR[14], FR[14], lminL, lmaxL, lminR, lmaxR;
-  Sys14::face_terms<D>(WL, p.sigma_lim, p.kws, UL, FL, lminL, lmaxL);
-  Sys14::face_terms<D>(WR, p.sigma_lim, p.kws, UR, FR, lminR, lmaxR);
-  double ULb[14], FLb[14], URb[14], FRb[14], lminLb, lmaxLb, lminRb, lmaxRb;
-  Adj14::interface_vjp(UL, FL, lminL, lmaxL, UR, FR, lminR, lmaxR, p.flux, Fb, ULb, FLb, lminLb,
-                       lmaxLb, URb, FRb, lminRb, lmaxRb);
+  double aF = 0.0, aU = 0.0, lmin, lmax;
+  {
+    double U[14], F[14];
+    Sys14::face_terms<D>(W, p.sigma_lim, p.kws, U, F, lmin, lmax);
 #pragma unroll
-  for (int v = 0; v < 14; ++v) {
-    rl[v * ns] = WL[v];
-    rl[(14 + v) * ns] = ULb[v];
-    rl[(28 + v) * ns] = FLb[v];
-    rr[v * ns] = WR[v];
-    rr[(14 + v) * ns] = URb[v];
-    rr[(28 + v) * ns] = FRb[v];
+    for (int v = 0; v < 14; ++v) { aF += Fhb[v] * F[v]; aU += Fhb[v] * U[v]; }
   }
-  rl[42 * ns] = lminLb; rl[43 * ns] = lmaxLb;
-  rr[42 * ns] = lminRb; rr[43 * ns] = lmaxRb;
-}
-
-template <int D>
-__global__ __launch_bounds__(ADJ_NT) void adj_face_b_kernel(AdjParams a) {
-  const StageParams& p = a.sp;
-  const long long nf = (D == 0) ? a.nfx : a.nfy;
-  const long long r = xcd_block() * ADJ_NT + threadIdx.x;
-  if (r >= 2 * nf) return;
-  const long long ns = a.nside;
-  const double* rec = a.side + r;
-  double Ub[14], Fb[14];
-  bool any = false;
+  // the partner lane's products and wave speeds
+  const double oF = __shfl_xor(aF, 1, 64), oU = __shfl_xor(aU, 1, 64);
+  const double omin = __shfl_xor(lmin, 1, 64), omax = __shfl_xor(lmax, 1, 64);
+  double Ub[14], Fb[14], lminb, lmaxb;
+  Adj14::interface_side_vjp(right, right ? omin : lmin, right ? omax : lmax, right ? lmin : omin,
+                            right ? lmax : omax, right ? oF : aF, right ? aF : oF, right ? oU : aU,
+                            right ? aU : oU, p.flux, Fhb, Ub, Fb, lminb, lmaxb);
+  bool any2 = lminb != 0.0 || lmaxb != 0.0;
 #pragma unroll
-  for (int v = 0; v < 14; ++v) {
-    Ub[v] = rec[(14 + v) * ns];
-    Fb[v] = rec[(28 + v) * ns];
-    any = any || Ub[v] != 0.0 || Fb[v] != 0.0;
-  }
-  const double lminb = rec[42 * ns], lmaxb = rec[43 * ns];
-  any = any || lminb != 0.0 || lmaxb != 0.0;
+  for (int v = 0; v < 14; ++v) any2 = any2 || Ub[v] != 0.0 || Fb[v] != 0.0;
   double Wb[14];
 #pragma unroll
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
-  if (any) {
-    double W[14];
+  if (any2) Adj14::face_terms_vjp<D>(W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
 #pragma unroll
-    for (int v = 0; v < 14; ++v) W[v] = rec[v * ns];
-    Adj14::face_terms_vjp<D>(W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
-  }
-  // face-state adjoints: [0,14) of the face's left state, [14,28) of its right state
-  double* out = (D == 0) ? a.fbx : a.fby;
-  const long long side = r / nf, fo = r % nf;
-#pragma unroll
-  for (int v = 0; v < 14; ++v) out[(side * 14 + v) * nf + fo] = Wb[v];
+  for (int v = 0; v < 14; ++v) out[v * nf] = Wb[v];
 }
 
 // ------------------------------------------------------------------ 2. extended cells
@@ -478,12 +449,9 @@ static hipError_t launch_adj_t(AdjParams& a, hipStream_t s) {
   hipLaunchKernelGGL((adj_prim_kernel<DIM>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
   if constexpr (ORDER == 2)
     hipLaunchKernelGGL((adj_limiter_kernel<DIM>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
-  hipLaunchKernelGGL((adj_face_a_kernel<0, DIM, ORDER>), blocks(a.nfx), dim3(ADJ_NT), 0, s, a);
-  hipLaunchKernelGGL((adj_face_b_kernel<0>), blocks(2 * a.nfx), dim3(ADJ_NT), 0, s, a);
-  if constexpr (DIM == 2) {
-    hipLaunchKernelGGL((adj_face_a_kernel<1, DIM, ORDER>), blocks(a.nfy), dim3(ADJ_NT), 0, s, a);
-    hipLaunchKernelGGL((adj_face_b_kernel<1>), blocks(2 * a.nfy), dim3(ADJ_NT), 0, s, a);
-  }
+  hipLaunchKernelGGL((adj_face_kernel<0, DIM, ORDER>), blocks(2 * a.nfx), dim3(ADJ_NT), 0, s, a);
+  if constexpr (DIM == 2)
+    hipLaunchKernelGGL((adj_face_kernel<1, DIM, ORDER>), blocks(2 * a.nfy), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL((adj_cell_kernel<DIM, ORDER>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL((adj_update_kernel<DIM>), dim3(a.n_upd_blocks), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(ADJ_NT), 0, s, a.part, a.n_upd_blocks, a.grad);

@@ -978,6 +978,77 @@ struct Adj14 {
     }
   }
 
+  // One side's share of interface_vjp, for two threads that each own one face state of the
+  // face.  Besides its own side it needs only both sides' wave speeds and the products
+  // aFL = Fhb . FL, aFR = Fhb . FR, aUL = Fhb . UL, aUR = Fhb . UR, which each side forms from
+  // its own U and F.  Same branches and tie rules as interface_vjp; the sums over the 14
+  // components are taken before the scalar factors are applied (rounding order differs).
+  template <class T>
+  MX_HD static void interface_side_vjp(bool right, T lminL, T lmaxL, T lminR, T lmaxR, T aFL, T aFR,
+                                       T aUL, T aUR, int flux_kind, const T* Fhb, T* Ub, T* Fb,
+                                       T& lminb, T& lmaxb) {
+    constexpr int NV = 14;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { Ub[v] = Fb[v] = T(0); }
+    lminb = lmaxb = T(0);
+    if (flux_kind == 0) {
+      T SL = tmin(lminL, lminR), SR = tmax(lmaxL, lmaxR);
+      if (SL >= T(0)) {
+        if (!right) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fb[v] = Fhb[v];
+        }
+      } else if (SR <= T(0)) {
+        if (right) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fb[v] = Fhb[v];
+        }
+      } else {
+        T inv = mrcp(SR - SL);
+        T SLR = SL * SR;
+        // F = (SR FL - SL FR + SL SR (UR - UL)) inv
+        T invb = SR * aFL - SL * aFR + SLR * (aUR - aUL);
+        T SRb = inv * aFL;
+        T SLb = -(inv * aFR);
+        T SLRb = inv * (aUR - aUL);
+        const T cF = right ? -SL : SR;
+        const T cU = right ? SLR : -SLR;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          T nb = Fhb[v] * inv;
+          Fb[v] = nb * cF;
+          Ub[v] = nb * cU;
+        }
+        SLb += SLRb * SR;
+        SRb += SLRb * SL;
+        T db = -invb * inv * inv;  // d/d(SR - SL)
+        SRb += db;
+        SLb -= db;
+        // SL = min(lminL, lminR), SR = max(lmaxL, lmaxR): the branch the forward took
+        if ((lminL < lminR) != right) lminb = SLb;
+        if ((lmaxL > lmaxR) != right) lmaxb = SRb;
+      }
+    } else {
+      T aL1 = tabs(lminL), aL2 = tabs(lmaxL), aR1 = tabs(lminR), aR2 = tabs(lmaxR);
+      T mL = tmax(aL1, aL2), mR = tmax(aR1, aR2);
+      T am = tmax(mL, mR);
+      T amb = -(T(0.5) * (aUR - aUL));
+      const T cU = right ? -(T(0.5) * am) : T(0.5) * am;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        Fb[v] = T(0.5) * Fhb[v];
+        Ub[v] = cU * Fhb[v];
+      }
+      // am = max(max(|lminL|, |lmaxL|), max(|lminR|, |lmaxR|)): the branch taken
+      if ((mL > mR) != right) {
+        const T a1 = right ? aR1 : aL1, a2 = right ? aR2 : aL2;
+        const T l1 = right ? lminR : lminL, l2 = right ? lmaxR : lmaxL;
+        if (a1 > a2) lminb = amb * (l1 < T(0) ? T(-1) : T(1));
+        else lmaxb = amb * (l2 < T(0) ? T(-1) : T(1));
+      }
+    }
+  }
+
   // face_flux<d> (HLL or Rusanov of two face states): WLb, WRb += ...
   template <int d, class T>
   MX_HD static void face_flux_vjp(const T* WL, const T* WR, T sigma_lim, T kws, int flux_kind,

@@ -31,8 +31,6 @@ struct AdjParams {
   int* vsx;                  // variable that selected it (-1: a constant factor) [eplane]
   int* vsy;
   int frozen_limiter;        // 1: no derivative through the limiter factors
-  double* side;              // per face side: W, U-bar, F-bar, lambda_min-bar, lambda_max-bar
-  long long nside;           //   [44][nside], nside = 2 max(nfx, nfy)
   double* part;              // per-workgroup partial sums [3][n_upd_blocks]
   int n_upd_blocks;
   double* grad;              // [3] accumulators: d/d jet Mach, d/d jet rho, d/d tau_ref

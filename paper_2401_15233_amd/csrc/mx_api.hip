@@ -60,7 +60,6 @@ struct TapeState {
   double* phiy = nullptr;
   int* vsx = nullptr;
   int* vsy = nullptr;
-  double* side = nullptr;
   double* part = nullptr;
   double* grad = nullptr;
   DevCtrl* actrl = nullptr;              // control block of the replayed stages
@@ -176,7 +175,7 @@ static void free_tape(maxent_solver* s) {
   for (double* p : t->ckpt) if (p) (void)hipFree(p);
   for (double* p : t->seg) if (p) (void)hipFree(p);
   for (double* p : t->lam) if (p) (void)hipFree(p);
-  double* bufs[] = {t->d_dt, t->fbx, t->fby, t->wb, t->wext, t->phix, t->phiy, t->side, t->part, t->grad};
+  double* bufs[] = {t->d_dt, t->fbx, t->fby, t->wb, t->wext, t->phix, t->phiy, t->part, t->grad};
   for (double* p : bufs) if (p) (void)hipFree(p);
   if (t->vsx) (void)hipFree(t->vsx);
   if (t->vsy) (void)hipFree(t->vsy);
@@ -618,7 +617,6 @@ static hipError_t adjoint_workspace(maxent_solver* s) {
   if (e == hipSuccess) e = hipMalloc(&t->phiy, (size_t)eplane * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&t->vsx, (size_t)eplane * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&t->vsy, (size_t)eplane * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&t->side, (size_t)44 * 2 * std::max(nfx, nfy) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&t->part, (size_t)3 * nb * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&t->grad, 3 * sizeof(double));
   for (auto& p : t->lam)
@@ -640,8 +638,7 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
     // leave the tape usable for the forward run; drop the partial workspace
     for (auto& p : t->seg) { if (p) (void)hipFree(p); p = nullptr; }
     for (auto& p : t->lam) { if (p) (void)hipFree(p); p = nullptr; }
-    double** bufs[] = {&t->fbx, &t->fby, &t->wb, &t->wext, &t->phix, &t->phiy, &t->side, &t->part,
-                       &t->grad};
+    double** bufs[] = {&t->fbx, &t->fby, &t->wb, &t->wext, &t->phix, &t->phiy, &t->part, &t->grad};
     for (double** p : bufs) { if (*p) (void)hipFree(*p); *p = nullptr; }
     int** ibufs[] = {&t->vsx, &t->vsy};
     for (int** p : ibufs) { if (*p) (void)hipFree(*p); *p = nullptr; }
@@ -691,8 +688,6 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   a.phiy = t->phiy;
   a.vsx = t->vsx;
   a.vsy = t->vsy;
-  a.side = t->side;
-  a.nside = 2 * std::max(a.nfx, a.nfy);
   a.frozen_limiter = s->adj_mode == MAXENT_ADJ_FROZEN_LIMITER ? 1 : 0;
   a.epitch = nx + 4;
   a.eplane = (long long)(nx + 4) * (dim == 2 ? ny + 4 : 1);

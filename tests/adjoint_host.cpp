@@ -116,7 +116,8 @@ int main(int argc, char** argv) {
   Stat s_c2p{"cons_to_prim"}, s_p2c{"prim_to_cons"}, s_ft0{"face_terms_x"}, s_ft1{"face_terms_y"},
       s_src_l{"source_local"}, s_src_c{"source_const"}, s_tau{"source_tau_ref"},
       s_hll{"face_flux_hll"}, s_rus{"face_flux_rusanov"}, s_rec_mm{"recon_minmod"},
-      s_rec_va{"recon_vanalbada"}, s_phi{"limiter_phi_equal"}, s_fd{"dual_vs_fd"};
+      s_rec_va{"recon_vanalbada"}, s_phi{"limiter_phi_equal"}, s_fd{"dual_vs_fd"},
+      s_side{"interface_side_split"}, s_side_l{"interface_side_speeds"};
   int hll_branch[3] = {0, 0, 0};
 
   for (int c = 0; c < n; ++c) {
@@ -202,6 +203,52 @@ int main(int argc, char** argv) {
         Sys14::face_terms<0>(WR, sl, kws, UR, FR, c2, d2);
         double SL = a < c2 ? a : c2, SR = b > d2 ? b : d2;
         hll_branch[SL >= 0 ? 0 : (SR <= 0 ? 1 : 2)]++;
+        // the interface reverse split over two threads, one per face state, against the
+        // whole; on the second pass both sides are the same state (every min / max a tie)
+        for (int tie = 0; tie < 2; ++tie) {
+          const double* uR = tie ? UL : UR;
+          const double* fR = tie ? FL : FR;
+          const double lR = tie ? a : c2, mR = tie ? b : d2;
+          for (int kind = 0; kind < 2; ++kind) {
+            double Fhb[14], ULb[14], FLb[14], URb[14], FRb[14], lLb, mLb, lRb, mRb;
+            for (int v = 0; v < 14; ++v) Fhb[v] = gauss();
+            Adj14::interface_vjp(UL, FL, a, b, uR, fR, lR, mR, kind, Fhb, ULb, FLb, lLb, mLb, URb, FRb,
+                                 lRb, mRb);
+            double aFL = 0, aFR = 0, aUL = 0, aUR = 0;
+            for (int v = 0; v < 14; ++v) {
+              aFL += Fhb[v] * FL[v]; aFR += Fhb[v] * fR[v];
+              aUL += Fhb[v] * UL[v]; aUR += Fhb[v] * uR[v];
+            }
+            // the U and F adjoints are the same products as in interface_vjp (compared exactly);
+            // the speed adjoints sum the 14 components before scaling, so they agree to the
+            // rounding of those sums: scale = the absolute sums they are formed from
+            double bFL = 0, bFR = 0, bU = 0;
+            for (int v = 0; v < 14; ++v) {
+              bFL += std::fabs(Fhb[v] * FL[v]); bFR += std::fabs(Fhb[v] * fR[v]);
+              bU += std::fabs(Fhb[v] * uR[v]) + std::fabs(Fhb[v] * UL[v]);
+            }
+            double sscale = 0.5 * bU;   // Rusanov: the speed adjoint is -(aUR - aUL) / 2
+            if (kind == 0) {
+              const double sL = a < lR ? a : lR, sR = b > mR ? b : mR;
+              const double inv = (sL < 0 && sR > 0) ? 1.0 / (sR - sL) : 0.0;
+              sscale = inv * (bFL + bFR) + inv * (std::fabs(sL) + std::fabs(sR)) * bU +
+                       inv * inv * (std::fabs(sR) * bFL + std::fabs(sL) * bFR + std::fabs(sL * sR) * bU);
+            }
+            for (int side = 0; side < 2; ++side) {
+              double Ub[14], Fb[14], lb, mb;
+              Adj14::interface_side_vjp(side == 1, a, b, lR, mR, aFL, aFR, aUL, aUR, kind, Fhb, Ub, Fb,
+                                        lb, mb);
+              const double* rU = side ? URb : ULb;
+              const double* rF = side ? FRb : FLb;
+              for (int v = 0; v < 14; ++v) {
+                s_side.add(rU[v], Ub[v], 1.0);
+                s_side.add(rF[v], Fb[v], 1.0);
+              }
+              s_side_l.add(side ? lRb : lLb, lb, sscale);
+              s_side_l.add(side ? mRb : mLb, mb, sscale);
+            }
+          }
+        }
       }
     }
 
@@ -279,7 +326,7 @@ int main(int argc, char** argv) {
     }
   }
   for (const Stat* st : {&s_c2p, &s_p2c, &s_ft0, &s_ft1, &s_src_l, &s_src_c, &s_tau, &s_hll, &s_rus,
-                         &s_rec_mm, &s_rec_va, &s_phi, &s_fd})
+                         &s_rec_mm, &s_rec_va, &s_phi, &s_fd, &s_side, &s_side_l})
     st->print();
   std::printf("hll_branches %d %d %d\n", hll_branch[0], hll_branch[1], hll_branch[2]);
   return 0;

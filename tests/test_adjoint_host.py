@@ -83,5 +83,17 @@ def test_dual_numbers_match_central_differences(results):
     assert n > 100 and err <= 1e-6
 
 
+def test_interface_reverse_split_over_two_threads(results):
+    """interface_side_vjp (each face state's share, from the pair's wave speeds and the flux
+    adjoint's products with both sides' U and F) equals interface_vjp's outputs for that side,
+    in every HLL case, for Rusanov, and with every min / max tied: the U and F adjoints bit for
+    bit, the wave-speed adjoints (sums over the components taken in another order) to within
+    1e-14 of the absolute sums they are formed from."""
+    err, n = results['interface_side_split']
+    assert n > 10000 and err == 0.0
+    err, n = results['interface_side_speeds']
+    assert n > 1000 and err <= 1e-14, err
+
+
 def test_every_hll_case_is_exercised(results):
     assert min(results['hll_branches']) > 0
