@@ -897,7 +897,7 @@ static hipError_t batch_enqueue(maxent_solver* s, int steps, hipStream_t st) {
   for (int k = 0; k < steps; ++k) {
     hipError_t e = mx::launch_batch_finalize(b->d_inst, b->d_order, b->n_inst, s->num.cfl,
                                              mx::tile_1d(b->nt * b->cpt), b->d_act_inst, b->d_act_tile0,
-                                             b->d_ctrl, st);
+                                             b->d_ctrl, grid, st);
     if (e != hipSuccess) return e;
     p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
     p.mode = mx::MODE_EULER; p.cdt = mid ? 0.5 : 1.0; p.do_cfl = 0;

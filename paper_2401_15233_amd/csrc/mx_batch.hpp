@@ -20,6 +20,8 @@ struct BatchInst {
 struct BatchCtrl {
   int n_active;                  // instances that advance in the current step
   int n_tiles;                   // their tiles: the work list of the step's stage launches
+  int per;                       // tiles per workgroup range of the stage launches (0: none)
+  int band;                      // ranges per XCD band (0: no bands, range = workgroup index)
 };
 
 struct BatchParams {
@@ -47,7 +49,8 @@ struct BatchParams {
 bool batch_shape_supported(int nt, int cpt);
 hipError_t launch_batch_stage(int precision, int nt, int cpt, const BatchParams& p, int grid, hipStream_t s);
 hipError_t launch_batch_finalize(BatchInst* in, const int* order, int n_inst, double cfl, int tile_w,
-                                 int* act_inst, int* act_tile0, BatchCtrl* bc, hipStream_t s);
+                                 int* act_inst, int* act_tile0, BatchCtrl* bc, int stage_grid,
+                                 hipStream_t s);
 hipError_t launch_batch_cfl(const BatchParams& p, long long total, hipStream_t s);
 
 }  // namespace mx
