@@ -111,7 +111,7 @@ __global__ __launch_bounds__(1024) void batch_finalize_kernel(BatchInst* in, con
     // in its L2.  While the ranges in use fill more than half of the grid the bands are the
     // grid's eighths; once they fill half or less (the end of a batch) the bands divide the
     // ranges in use, which would otherwise all fall on the first XCDs (measured on one
-    // 546-tile tube: 85 -> 43 us per step)
+    // 546-tile tube: 85 -> 37.5 us per step)
     const int per = (n_tiles + nb - 1) / nb;
     int band = 0;
     if (nb % 8 == 0 && per > 0) {
