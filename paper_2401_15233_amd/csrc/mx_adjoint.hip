@@ -11,11 +11,11 @@
 //   1. faces, per direction (adj_face_kernel, two threads per face, one per face state):
 //      each thread takes the flux adjoint Fb = (mu_right - mu_left) / dx from the two
 //      adjacent cells (mu = mu_coef dt lam_out, zero in ghost cells), rebuilds its face state
-//      and evaluates its closure, wave speeds, flux and conserved state; the two threads
-//      exchange their wave speeds and the products Fb . F, Fb . U (lane shuffles), which is
-//      all the reverse of the HLL / Rusanov combination (branch replayed) needs besides the
-//      thread's own side; then each thread reverses closure, wave speeds, physical flux and
-//      conserved map of its own face state;
+//      and evaluates its closure (kept for the reverse), wave speeds, flux and conserved
+//      state; the two threads exchange their wave speeds and the products Fb . F, Fb . U
+//      (lane shuffles), which is all the reverse of the HLL / Rusanov combination (branch
+//      replayed) needs besides the thread's own side; then each thread reverses closure, wave
+//      speeds, physical flux and conserved map of its own face state;
 //   2. extended cells (adj_cell_kernel): for every cell of the domain and its two ghost
 //      layers, gather the reverse of the limited reconstruction of the up to three stencil
 //      cells whose face states it feeds (limiter argmin, regime and fallback replayed);
@@ -168,13 +168,21 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
   } else {
     get_w(a, ext_idx<D, DIM>(a, cc, l), W);
   }
+  // forward face terms (Sys14::face_terms, step by step): the closure core and closing values
+  // are kept for the reverse below
+  Sys14::Core<double> k;
+  Sys14::core(W, p.sigma_lim, k);
+  double Qd[6], Rd[3], Sd;
+  Sys14::closure_dir<D>(k, Qd, Rd, Sd);
   double aF = 0.0, aU = 0.0, lmin, lmax;
   {
     double U[14], F[14];
-    Sys14::face_terms<D>(W, p.sigma_lim, p.kws, U, F, lmin, lmax);
+    Sys14::flux<D>(W, Qd, Rd, Sd, F);
+    Sys14::prim_to_cons(W, U);
 #pragma unroll
     for (int v = 0; v < 14; ++v) { aF += Fhb[v] * F[v]; aU += Fhb[v] * U[v]; }
   }
+  Sys14::wavespeeds<D>(k, W[1 + D], p.kws, lmin, lmax);
   // the partner lane's products and wave speeds
   const double oF = __shfl_xor(aF, 1, 64), oU = __shfl_xor(aU, 1, 64);
   const double omin = __shfl_xor(lmin, 1, 64), omax = __shfl_xor(lmax, 1, 64);
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
   double Wb[14];
 #pragma unroll
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
-  if (any2) Adj14::face_terms_vjp<D>(W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
+  if (any2) Adj14::face_terms_vjp_prepared<D>(k, Qd, Rd, Sd, W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
 #pragma unroll
   for (int v = 0; v < 14; ++v) out[v * nf] = Wb[v];
 }

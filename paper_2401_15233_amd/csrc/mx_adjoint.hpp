@@ -681,6 +681,15 @@ struct Adj14 {
     S::core(W, sigma_lim, k);
     T Qd[6], Rd[3], Sd;
     S::closure_dir<d>(k, Qd, Rd, Sd);
+    face_terms_vjp_prepared<d>(k, Qd, Rd, Sd, W, sigma_lim, kws, Ub, Fb, lminb, lmaxb, Wb);
+  }
+
+  // the same reverse from the forward's own core k = core(W) and closing values
+  // (Qd, Rd, Sd) = closure_dir<d>(k), for a caller that has just evaluated them
+  template <int d, class T>
+  MX_HD static void face_terms_vjp_prepared(const typename S::template Core<T>& k, const T* Qd,
+                                            const T* Rd, T Sd, const T* W, T sigma_lim, T kws,
+                                            const T* Ub, const T* Fb, T lminb, T lmaxb, T* Wb) {
     T Qdb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T Rdb[3] = {T(0), T(0), T(0)};
     T Sdb = T(0);
