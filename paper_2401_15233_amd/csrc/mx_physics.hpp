@@ -46,6 +46,13 @@ template <class T> MX_HD T sq(T a) { return a * a; }
 template <class T> MX_HD T tmax(T a, T b) { return a > b ? a : b; }
 template <class T> MX_HD T tmin(T a, T b) { return a < b ? a : b; }
 template <class T> MX_HD T tabs(T a) { return a < T(0) ? -a : a; }
+#if defined(__HIP_DEVICE_COMPILE__)
+// on the device: clearing the sign bit is one instruction where the compare and select take
+// three; it also maps -0 to +0, so a magnitude (a CFL rate reduced as a positive bit pattern)
+// is never negative zero
+template <> MX_HD double tabs<double>(double a) { return __builtin_fabs(a); }
+template <> MX_HD float tabs<float>(float a) { return __builtin_fabsf(a); }
+#endif
 
 // FP64 square root, reciprocal and quotient.  On the device: the hardware reciprocal /
 // reciprocal-square-root seed (single-precision accurate) refined by Newton-Raphson -- two
