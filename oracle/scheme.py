@@ -92,10 +92,6 @@ class Setup:
         return (self.y1 - self.y0) / self.ny
 
 
-class OracleFailure(RuntimeError):
-    pass
-
-
 # ----------------------------------------------------------------------------- states
 def cons_to_prim(U, s):
     return mo.cons_to_prim5(U) if s.system == 5 else mo.cons_to_prim14(U)
@@ -347,13 +343,25 @@ def cfl_dt(U, s):
     return s.cfl / (cell_lambda(U, s, 0) / s.dx + cell_lambda(U, s, 1) / s.dy).max()
 
 
+class OracleFailure(RuntimeError):
+    """A failed step: `step` is its 1-based index, `reason` 'nonfinite' or 'unrealizable'."""
+
+    def __init__(self, msg, step=0, reason=''):
+        super().__init__(msg)
+        self.step = step
+        self.reason = reason
+
+
 def check_state(U, s, step):
-    """Failure on a non-finite value, rho <= 0 or a non-SPD pressure at a cell centre."""
+    """Failure on a non-finite value, rho <= 0 or a non-SPD pressure at a cell centre of a
+    stage's new state (reading: checked per stage, since the next stage evaluates the
+    closure of the intermediate state)."""
     if not np.all(np.isfinite(U)):
-        raise OracleFailure(f'non-finite state after step {step}')
+        raise OracleFailure(f'non-finite state in step {step}', step, 'nonfinite')
     W = cons_to_prim(U, s)
     if not np.all(_admissible(W, s)):
-        raise OracleFailure(f'unrealizable state (rho <= 0 or P not SPD) after step {step}')
+        raise OracleFailure(f'unrealizable state (rho <= 0 or P not SPD) in step {step}', step,
+                            'unrealizable')
 
 
 def relax_backward_euler(Ut, h_dt, s, tau_ref):
@@ -379,22 +387,33 @@ def relax_backward_euler(Ut, h_dt, s, tau_ref):
     return (Ut + h * prim_to_cons(Weq, s)) / (1.0 + h)
 
 
-def step(U, dt, s, tau_ref, stats=None):
-    """One full time step with the configured integrator (ghosts refilled per stage)."""
+def step(U, dt, s, tau_ref, stats=None, check=None):
+    """One full time step with the configured integrator (ghosts refilled per stage).
+    `check`, if given, is called with every stage's new state (the intermediate state of a
+    two-stage integrator and the step's result): the closure of an intermediate state is
+    evaluated by the next stage, so an unrealizable one is a failure of the step."""
+    chk = check if check is not None else (lambda V: None)
     if s.source_implicit:
         if s.integrator != 'fe':
             raise ValueError('the implicit source is defined for forward Euler')
-        return relax_backward_euler(U + dt * residual(U, s, 0.0, stats), dt, s, tau_ref)
+        out = relax_backward_euler(U + dt * residual(U, s, 0.0, stats), dt, s, tau_ref)
+        chk(out)
+        return out
     L0 = residual(U, s, tau_ref, stats)
     if s.integrator == 'fe':
-        return U + dt * L0
-    if s.integrator == 'ssprk2':
+        out = U + dt * L0
+    elif s.integrator == 'ssprk2':
         Us = U + dt * L0
-        return 0.5 * U + 0.5 * (Us + dt * residual(Us, s, tau_ref, stats))
-    if s.integrator == 'midpoint':
+        chk(Us)
+        out = 0.5 * U + 0.5 * (Us + dt * residual(Us, s, tau_ref, stats))
+    elif s.integrator == 'midpoint':
         Us = U + (0.5 * dt) * L0
-        return U + dt * residual(Us, s, tau_ref, stats)
-    raise ValueError(s.integrator)
+        chk(Us)
+        out = U + dt * residual(Us, s, tau_ref, stats)
+    else:
+        raise ValueError(s.integrator)
+    chk(out)
+    return out
 
 
 def run(U, s, tau_ref, nsteps=None, t_end=None, dt=None, t0=0.0, record=None,
@@ -411,13 +430,12 @@ def run(U, s, tau_ref, nsteps=None, t_end=None, dt=None, t0=0.0, record=None,
         h = cfl_dt(U, s) if dt is None else dt
         if t_end is not None:
             h = min(h, t_end - t)
-        U = step(U, h, s, tau_ref)
+        U = step(U, h, s, tau_ref,
+                 check=(lambda V, k=n + 1: check_state(V, s, k)) if check else None)
         t += h
         n += 1
         if record is not None:
             record.append(h)
-        if check:
-            check_state(U, s, n)
     return U, t, n
 
 

@@ -1,11 +1,14 @@
 """Limits and degenerate calls on the device: an allocation beyond the card's memory reports
 NOMEM and leaves a usable library behind; a zero-step call is a no-op; the smallest grids
-(4 cells per axis, less than one tile) step like the oracle."""
+(4 cells per axis, less than one tile) step like the oracle; a failing first stage is
+reported in the same step, for the same reason, as by the oracle."""
 import numpy as np
 import pytest
 
 from paper_2401_15233_amd import inputs as I
-from test_gpu_parity import compare
+from oracle import scheme as sc
+import oracle_bridge as ob
+from test_gpu_parity import compare, gpu_run
 
 pytestmark = pytest.mark.gpu
 
@@ -42,9 +45,7 @@ def test_zero_steps_is_a_no_op(gpu_lib):
     (dict(system=14, dim=1, nx=4, order=2, integrator='ssprk2', flux='hll', cfl=0.5,
           limiter='minmod', bc=('periodic', 'periodic', 'transmissive', 'transmissive')),
      I.sod_prims(14, 4)),
-    # CFL 0.2: at 0.4 the first SSP-RK2 stage of this coarse random field already has a cell
-    # whose P is not positive definite (the library checks every stage and reports it; the
-    # oracle checks whole steps, and the averaged second stage happens to be admissible again)
+    # CFL 0.2 (at 0.4 the first stage fails: test_stage_failure_reported_like_the_oracle)
     (dict(system=14, dim=2, nx=4, ny=4, order=2, integrator='ssprk2', flux='rusanov', cfl=0.2,
           limiter='vanalbada', bc=('reflective', 'transmissive', 'periodic', 'periodic')),
      I.random_smooth_field14(4, 4, seed=3)),
@@ -52,3 +53,19 @@ def test_zero_steps_is_a_no_op(gpu_lib):
 def test_smallest_grids_against_oracle(gpu_lib, kw, W0):
     compare(f"{kw['system']}-moment {kw['dim']}D {kw['nx']} cells", gpu_lib, kw, W0, 5,
             tau_ref=0.02)
+
+
+def test_stage_failure_reported_like_the_oracle(gpu_lib):
+    """At CFL 0.4 the first SSP-RK2 stage of this coarse random field has a cell whose P is
+    not positive definite.  Both sides check every stage's new state (the second stage would
+    evaluate the closure of the intermediate state), so both report an unrealizable state in
+    step 1, although the averaged second stage happens to be admissible again."""
+    kw = dict(system=14, dim=2, nx=4, ny=4, order=2, integrator='ssprk2', flux='rusanov', cfl=0.4,
+              limiter='vanalbada', bc=('reflective', 'transmissive', 'periodic', 'periodic'))
+    W0 = I.random_smooth_field14(4, 4, seed=3)
+    with pytest.raises(sc.OracleFailure) as e:
+        ob.oracle_run(kw, W0, nsteps=5, tau_ref=0.02)
+    _, info = gpu_run(gpu_lib, kw, W0, 5, tau_ref=0.02, check=False)
+    print(f'oracle: {e.value}; gpu: {info["status"]} in step {info["fail_step"]}', flush=True)
+    assert e.value.step == 1 and e.value.reason == 'unrealizable'
+    assert info['status'] == 'UNREALIZABLE' and info['fail_step'] == 1

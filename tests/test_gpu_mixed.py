@@ -3,15 +3,15 @@ near the Junk subspace and the realizability boundary; FP64 state, reconstructio
 dissipation and update) against the FP64 oracle.  The error is stated per moment in L1,
 relative to the oracle's L1 norm; conservation stays at FP64 round-off.
 
-Bar: L1 error <= max(2e-6, 10 x spread), where the spread is the larger of two changes of
-the oracle's own L1 result (computed by the oracle alone): (a) when its input is perturbed
-by +-2^-24 relative, and (b) when every physical flux and wave speed it evaluates carries
-one random +-2^-24 relative rounding -- what single-precision flux evaluation does to an
-otherwise exact computation at every stage.  On smooth flows both are ~1e-7 and the bar is
-the floor; the developed crossed-jets field is so sensitive (common-limiter switching in the
-beam tails, near-Junk wave speeds) that an FP32-sized perturbation moves the oracle itself by
-~1e-2 in L1; the jets entering a 1e-3 background respond to per-stage flux rounding at the
-front (b) far more than to an input perturbation (a)."""
+Bar: L1 error <= max(2e-6, 2 x spread), where the spread is the largest change of the
+oracle's own L1 result (computed by the oracle alone) when every physical flux and wave
+speed it evaluates carries one random +-2^-24 relative rounding -- what single-precision
+flux evaluation does to an otherwise exact FP64 computation at every stage.  The mixed path
+keeps the state, primitive recovery and reconstruction in FP64, so an input rounding to
+single precision does not describe it and is not part of the bar.  On smooth flows the
+spread is ~1e-7 and the bar is the floor; on the developed crossed-jets field the jets
+entering the 1e-3 background respond to per-stage flux rounding at the front, and the bar
+follows that response."""
 import numpy as np
 import pytest
 
@@ -26,7 +26,10 @@ JETS = dict(system=14, dim=2, order=2, integrator='ssprk2', flux='hll', cfl=0.4,
             jets=[(0.35, 0.1, 30.0), (0.65, 0.1, -30.0)], jet_mach=3.0, jet_rho=1.0, jet_T=1.0)
 TAU_JET = I.kn_to_tau_ref(0.1, L_ref=0.1)
 L1_FLOOR = 2e-6
-FP32_PERTURB = 2.0 ** -24
+
+
+def fmt(a):
+    return '[' + ' '.join(f'{x:.1e}' for x in np.asarray(a)) + ']'
 
 
 def l1_rel(a, b):
@@ -52,20 +55,16 @@ def test_mixed_jets_l1_error_against_fp64_oracle(gpu_lib, field):
     n = 4 if field == 'developed' else 15
     kw = dict(JETS, nx=nx, ny=ny)
     Um, info = run(gpu_lib, dict(kw, precision='mixed'), W0, n, tau_ref=TAU_JET)
-    base, spread, t, no, _ = ob.oracle_with_l1_spread(kw, W0, 0.0, TAU_JET, trials=2,
-                                                      perturb=FP32_PERTURB, nsteps=n)
-    _, fspread = ob.oracle_with_flux_rounding_spread(kw, W0, TAU_JET, n, trials=2)
-    spread = np.maximum(spread, fspread)
+    base, fspread = ob.oracle_with_flux_rounding_spread(kw, W0, TAU_JET, n, trials=2)
     b1 = np.maximum(np.abs(base).reshape(14, -1).sum(1), 1e-300)
     err = l1_rel(Um, base)
-    sp = spread / b1
+    bar = np.maximum(L1_FLOOR, 2 * fspread / b1)
     frac = info['n_fp64_states'] / max(info['n_face_states'], 1)
-    print(f'mixed jets {field} {n} steps: L1 relative error per moment '
-          f'{np.array2string(err, precision=1)}; oracle FP32-rounding L1 spread '
-          f'{np.array2string(sp, precision=1, floatmode="maxprec_equal")}; FP64 re-evaluated face states {frac:.4f}',
-          flush=True)
+    print(f'mixed jets {field} {n} steps: L1 relative error per moment {fmt(err)}; '
+          f'oracle flux-rounding L1 spread {fmt(fspread / b1)}; bar {fmt(bar)}; '
+          f'FP64 re-evaluated face states {frac:.4f}', flush=True)
     assert info['n_face_states'] > 0
-    assert np.all(err <= np.maximum(L1_FLOOR, 10 * sp))
+    assert np.all(err <= bar)
 
 
 def test_mixed_sod14_l1_error_against_fp64_oracle(gpu_lib):
@@ -74,16 +73,14 @@ def test_mixed_sod14_l1_error_against_fp64_oracle(gpu_lib):
     W0 = I.sod_prims(14, nx)
     tau = I.kn_to_tau_ref(0.01)
     Um, info = run(gpu_lib, dict(kw, precision='mixed'), W0, 100, tau_ref=tau)
-    base, spread, t, n, _ = ob.oracle_with_l1_spread(kw, W0, 0.0, tau, trials=2,
-                                                     perturb=FP32_PERTURB, nsteps=100)
-    _, fspread = ob.oracle_with_flux_rounding_spread(kw, W0, tau, 100, trials=2)
-    spread = np.maximum(spread, fspread)
+    base, fspread = ob.oracle_with_flux_rounding_spread(kw, W0, tau, 100, trials=2)
     b1 = np.maximum(np.abs(base).reshape(14, -1).sum(1), 1e-300)
     err = l1_rel(Um, base)
-    print(f'mixed sod14 100 steps: L1 relative error {np.array2string(err, precision=1)}; '
-          f'oracle FP32-perturbation spread {np.array2string(spread / b1, precision=1)}', flush=True)
+    bar = np.maximum(L1_FLOOR, 2 * fspread / b1)
+    print(f'mixed sod14 100 steps: L1 relative error {fmt(err)}; oracle flux-rounding L1 '
+          f'spread {fmt(fspread / b1)}; bar {fmt(bar)}', flush=True)
     live = [0, 1, 4, 7, 9, 10, 13]
-    assert np.all(err[live] <= np.maximum(L1_FLOOR, 10 * spread[live] / b1[live]))
+    assert np.all(err[live] <= bar[live])
 
 
 def test_mixed_periodic_conservation_fp64_level(gpu_lib):
