@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MAXENT_ABI_VERSION 2
+#define MAXENT_ABI_VERSION 3
 
 typedef struct maxent_solver maxent_solver;
 
@@ -47,12 +47,14 @@ typedef enum {
 
 enum { MAXENT_BC_TRANSMISSIVE = 0, MAXENT_BC_PERIODIC = 1, MAXENT_BC_REFLECTIVE = 2,
        MAXENT_BC_JET = 3 };
-enum { MAXENT_FP64 = 0, MAXENT_MIXED = 2 };
+enum { MAXENT_FP64 = 0, MAXENT_FP32 = 1, MAXENT_MIXED = 2 };
 enum { MAXENT_MINMOD = 0, MAXENT_VANALBADA = 1 };
 enum { MAXENT_HLL = 0, MAXENT_RUSANOV = 1 };
 enum { MAXENT_FE = 0, MAXENT_SSPRK2 = 1, MAXENT_MIDPOINT = 2 };
 enum { MAXENT_TAU_LOCAL = 0, MAXENT_TAU_CONST = 1 };
-enum { MAXENT_PRIMITIVE = 0, MAXENT_CONSERVED = 1, MAXENT_SIGMA = 2 };
+enum { MAXENT_PRIMITIVE = 0, MAXENT_CONSERVED = 1, MAXENT_SIGMA = 2, MAXENT_CLOSING = 3 };
+/* components per cell of a MAXENT_CLOSING read-back of the 14-moment system */
+#define MAXENT_CLOSING_COMPONENTS_14 19
 
 /* Problem definition.
  *   system        5 (1D1V, requires dim = 1) or 14.
@@ -86,12 +88,15 @@ typedef struct {
 } maxent_problem;
 
 /* Numerics.
- *   precision     MAXENT_FP64, or MAXENT_MIXED: state, primitive recovery, reconstruction,
+ *   precision     MAXENT_FP64; MAXENT_MIXED: state, primitive recovery, reconstruction,
  *                 HLL dissipation and update in FP64; closure, wave speeds and physical
  *                 fluxes of each face state in FP32 (the dimensionless closure is robust in
  *                 single precision, Section 3.3), re-evaluated in FP64 near the Junk
  *                 subspace (A < -1e-3, sigma < 1e-2) and the realizability boundary
- *                 (sigma > 0.999).
+ *                 (sigma > 0.999); MAXENT_FP32: every face-state evaluation (closure, wave
+ *                 speeds, physical fluxes, the HLL / Rusanov combination) in FP32 with no
+ *                 FP64 re-evaluation, state, primitive recovery, reconstruction, source and
+ *                 update in FP64 (single solvers only; the batch takes FP64 or MIXED).
  *   order         1 (first order, cell states at faces) or 2 (MUSCL on primitives with one
  *                 common, most stringent limiter factor, Section 3.2).
  *   limiter       MINMOD or VANALBADA (the paper's choice).
@@ -130,7 +135,13 @@ typedef struct {
   int fail_step;            /* first failing step index (1-based), 0 if none         */
   int fail_code;            /* bit 1: non-finite, bit 2: rho <= 0 / P not SPD        */
   long long n_fp64_states;  /* MIXED: face states re-evaluated in FP64 since init    */
-  long long n_face_states;  /* MIXED: face states evaluated since init (tile faces)  */
+  long long n_face_states;  /* MIXED, FP32: face states evaluated since init          */
+  long long n_sigma_limited; /* cells of the current state whose unlimited sigma is
+                                below sigma_lim (Appendix A: the closure then uses
+                                sigma_lim); counted by maxent_get_info, -1 from
+                                maxent_step                                          */
+  double fp64_fraction;     /* share of face-state evaluations done in FP64: 1 for FP64,
+                               n_fp64_states / n_face_states for MIXED, 0 for FP32      */
 } maxent_info;
 
 /* Allocate a solver.  `stream` is a hipStream_t (NULL for the default stream).
@@ -160,12 +171,20 @@ int maxent_init_state(maxent_solver* s, int repr, const double* src, int src_on_
 int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, double t_end,
                 maxent_info* info);
 
-/* Copy out a field.  repr = PRIMITIVE or CONSERVED (nv x ny x nx doubles) or SIGMA (the
- * unlimited parabolic-mapping parameter, ny x nx).  dst is host (dst_on_device = 0) or
- * device memory owned by the caller.  Synchronises the solver's stream. */
+/* Copy out a field.  repr = PRIMITIVE or CONSERVED (nv x ny x nx doubles), SIGMA (the
+ * unlimited parabolic-mapping parameter, ny x nx) or CLOSING: the closing moments of each
+ * cell state, dimensional, at sigma_bar = max(sigma, sigma_lim) (eqs.
+ * closure-14mom-Qijk-approx, -Rijkk-approx, -Sijjkk-approx; eq. closure-1D1V-s-approx):
+ * 14 moments: MAXENT_CLOSING_COMPONENTS_14 x ny x nx doubles, in the order
+ *   Q_ijk  xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz (10),
+ *   R_ijkk xx xy xz yy yz zz (6), S_ijjkk x y z (3);
+ * 5 moments: s (ny x nx).  dst is host (dst_on_device = 0) or device memory owned by the
+ * caller.  Synchronises the solver's stream. */
 int maxent_get_moments(maxent_solver* s, int repr, double* dst, int dst_on_device);
 
-/* Number of components (5 or 14), time and step count of a solver. */
+/* Number of components (5 or 14); time, step count and counters of a solver (also counts
+ * the sigma-limited cells of the current state: one pass over the field).  Synchronises the
+ * solver's stream. */
 int maxent_num_vars(const maxent_solver* s);
 int maxent_get_info(maxent_solver* s, maxent_info* info);
 

@@ -147,7 +147,8 @@ static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
   }
   if (p.tau_mode != MAXENT_TAU_LOCAL && p.tau_mode != MAXENT_TAU_CONST) return "bad tau_mode";
   if (p.tau_mode == MAXENT_TAU_LOCAL && !(p.rho_ref > 0 && p.T_ref > 0)) return "bad rho_ref/T_ref";
-  if (n.precision != MAXENT_FP64 && n.precision != MAXENT_MIXED) return "unsupported precision";
+  if (n.precision != MAXENT_FP64 && n.precision != MAXENT_FP32 && n.precision != MAXENT_MIXED)
+    return "unsupported precision";
   if (n.order != 1 && n.order != 2) return "order must be 1 or 2";
   if (n.limiter != MAXENT_MINMOD && n.limiter != MAXENT_VANALBADA) return "bad limiter";
   if (n.flux != MAXENT_HLL && n.flux != MAXENT_RUSANOV) return "bad flux";
@@ -228,7 +229,9 @@ extern "C" int maxent_create(const maxent_problem* problem, const maxent_numeric
   s->pitch = ((problem->nx + 15) / 16) * 16;   // rows start on 128-byte boundaries
   s->plane = (long long)problem->ny * s->pitch;
   size_t field = (size_t)s->nv * s->plane * sizeof(double);
-  size_t flat = (size_t)s->nv * problem->nx * problem->ny * sizeof(double);
+  // unpadded staging: a field of nv components, or the closing moments (19 per 14-moment cell)
+  const int n_stage = s->nv == 14 ? MAXENT_CLOSING_COMPONENTS_14 : s->nv;
+  size_t flat = (size_t)n_stage * problem->nx * problem->ny * sizeof(double);
   hipError_t e = hipGetDevice(&s->device);
   if (e == hipSuccess) e = hipMalloc(&s->U, field);
   if (e == hipSuccess) e = hipMalloc(&s->Us, field);
@@ -279,8 +282,12 @@ static mx::StageParams stage_params(maxent_solver* s, double tau_ref) {
   return p;
 }
 
+static int stage_precision(const maxent_numerics& n) {
+  return n.precision == MAXENT_MIXED ? 1 : (n.precision == MAXENT_FP32 ? 2 : 0);
+}
+
 static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::StageParams& p) {
-  const int prec = s->num.precision == MAXENT_MIXED ? 1 : 0;
+  const int prec = stage_precision(s->num);
   if (!s->prof) return mx::launch_stage(sys, dim, ord, prec, p, s->stream);
   while (s->ev.size() < s->ev_used + 2) {
     hipEvent_t e;
@@ -338,6 +345,9 @@ static void fill_info(maxent_solver* s, maxent_info* info) {
   info->fail_code = c.status;
   info->n_fp64_states = c.n_fp64;
   info->n_face_states = c.n_states;
+  info->n_sigma_limited = -1;     // counted by maxent_get_info only
+  info->fp64_fraction = c.n_states > 0 ? (double)c.n_fp64 / (double)c.n_states
+                                       : (s->num.precision == MAXENT_FP64 ? 1.0 : 0.0);
 }
 
 static mx::BatchParams batch_params(maxent_solver* s) {
@@ -497,21 +507,31 @@ extern "C" int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, d
 
 extern "C" int maxent_get_info(maxent_solver* s, maxent_info* info) {
   if (!s || !info) return MAXENT_E_INVAL;
+  if (s->ready || s->batch) {
+    HIP_TRY(s, hipMemsetAsync(&s->ctrl->n_sigma_limited, 0, sizeof(long long), s->stream));
+    HIP_TRY(s, mx::launch_count_sigma_limited(s->prob.system, s->U, s->prob.nx, s->prob.ny, s->pitch,
+                                              s->num.sigma_lim, s->ctrl, s->stream));
+  }
   int rc = read_ctrl(s);
   if (rc) return rc;
   fill_info(s, info);
+  info->n_sigma_limited = (s->ready || s->batch) ? s->ctrl_host->n_sigma_limited : 0;
   return MAXENT_OK;
 }
 
 extern "C" int maxent_get_moments(maxent_solver* s, int repr, double* dst, int dst_on_device) {
   if (!s) return MAXENT_E_INVAL;
   if (!dst) return fail(s, MAXENT_E_INVAL, "null dst");
-  if (repr != MAXENT_PRIMITIVE && repr != MAXENT_CONSERVED && repr != MAXENT_SIGMA)
-    return fail(s, MAXENT_E_INVAL, "repr must be PRIMITIVE, CONSERVED or SIGMA");
+  if (repr != MAXENT_PRIMITIVE && repr != MAXENT_CONSERVED && repr != MAXENT_SIGMA &&
+      repr != MAXENT_CLOSING)
+    return fail(s, MAXENT_E_INVAL, "repr must be PRIMITIVE, CONSERVED, SIGMA or CLOSING");
   size_t cells = (size_t)s->prob.nx * s->prob.ny;
-  size_t bytes = (repr == MAXENT_SIGMA ? 1 : (size_t)s->nv) * cells * sizeof(double);
+  size_t comps = (size_t)s->nv;
+  if (repr == MAXENT_SIGMA) comps = 1;
+  if (repr == MAXENT_CLOSING) comps = s->nv == 14 ? MAXENT_CLOSING_COMPONENTS_14 : 1;
+  size_t bytes = comps * cells * sizeof(double);
   HIP_TRY(s, mx::launch_egress(s->prob.system, repr, s->U, s->stage, s->prob.nx, s->prob.ny,
-                               s->pitch, s->stream));
+                               s->pitch, s->num.sigma_lim, s->stream));
   HIP_TRY(s, hipMemcpyAsync(dst, s->stage, bytes,
                             dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -811,6 +831,8 @@ extern "C" int maxent_create_batch(const maxent_problem* common, const maxent_nu
   if (num->order != 2) return fail(nullptr, MAXENT_E_INVAL, "batched tubes use the second-order scheme");
   if (num->integrator != MAXENT_SSPRK2 && num->integrator != MAXENT_MIDPOINT)
     return fail(nullptr, MAXENT_E_INVAL, "batched tubes use SSPRK2 or MIDPOINT");
+  if (num->precision != MAXENT_FP64 && num->precision != MAXENT_MIXED)
+    return fail(nullptr, MAXENT_E_INVAL, "batched tubes use FP64 or MIXED precision");
   long long total = 0;
   for (int i = 0; i < n_inst; ++i) {
     if (inst[i].n_cells < 4) return fail(nullptr, MAXENT_E_INVAL, "every instance needs >= 4 cells");

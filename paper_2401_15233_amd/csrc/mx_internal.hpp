@@ -19,6 +19,7 @@ struct DevCtrl {
   int fail_step;                 // first failing step (0: none)
   long long n_fp64;              // mixed precision: face states re-evaluated in FP64
   long long n_states;            // mixed precision: face states evaluated
+  long long n_sigma_limited;     // cells with sigma < sigma_lim (set by the counting kernel)
 };
 
 // 1D tiles: a workgroup of NT threads owns NT - 4 cells, so that the cells plus the two-cell
@@ -74,7 +75,11 @@ hipError_t launch_ctrl_reset(DevCtrl* c, double t0, hipStream_t s);
 // src/dst: unpadded [nv][ny][nx]; U: padded [nv][ny][pitch]
 hipError_t launch_ingest(int system, int repr, const double* src, double* U, int nx, int ny,
                          int pitch, DevCtrl* c, hipStream_t s);
+// repr 0 primitive, 1 conserved, 2 sigma, 3 closing moments (19 values per 14-moment cell)
 hipError_t launch_egress(int system, int repr, const double* U, double* dst, int nx, int ny,
-                         int pitch, hipStream_t s);
+                         int pitch, double sigma_lim, hipStream_t s);
+// zero ctrl->n_sigma_limited first; adds the cells of U with sigma < sigma_lim
+hipError_t launch_count_sigma_limited(int system, const double* U, int nx, int ny, int pitch,
+                                      double sigma_lim, DevCtrl* c, hipStream_t s);
 
 }  // namespace mx

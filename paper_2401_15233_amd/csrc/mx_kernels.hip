@@ -1,4 +1,4 @@
-// gfx950 kernels of the finite-volume step (FP64).
+// gfx950 kernels of the finite-volume step (FP64; FP32 / mixed face evaluation by template).
 //
 // One fused kernel per Runge-Kutta stage.  A workgroup owns a TX x TY tile of cells and
 //   1. loads the tile plus a G-cell halo of the stage input U (structure of arrays, x
@@ -149,7 +149,8 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
     }
     double Fh[NV];
     if constexpr (PREC == 0) face_flux<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh);
-    else face_flux_mixed<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh, n64);
+    else if constexpr (PREC == 1) face_flux_mixed<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh, n64);
+    else face_flux_fp32<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh);
     nstates += 2;
 #pragma unroll
     for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
@@ -173,7 +174,8 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       }
       if constexpr (SYS::NV == 14) {
         if constexpr (PREC == 0) face_flux<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
-        else face_flux_mixed<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy, n64);
+        else if constexpr (PREC == 1) face_flux_mixed<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy, n64);
+        else face_flux_fp32<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
       }
       nstates += 2;
     }
@@ -263,13 +265,13 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   // block reductions: status, fallback count, CFL rate
   flag = wave_or(flag);
   nfb = wave_sum(nfb);
-  if constexpr (PREC != 0) n64 = wave_sum(n64);
+  if constexpr (PREC == 1) n64 = wave_sum(n64);
   nstates = wave_sum(nstates);
   const int lane = t & 63, wid = t >> 6;
   if (lane == 0) {
     if (flag) atomicOr(&sFlag[0], flag);
     if (nfb) atomicAdd(&sFlag[1], nfb);
-    if (PREC != 0 && n64) atomicAdd(&sFlag[2], n64);
+    if (PREC == 1 && n64) atomicAdd(&sFlag[2], n64);
   }
   if (p.do_cfl) {
     rate = wave_max(rate);
@@ -361,7 +363,7 @@ __global__ void ctrl_reset_kernel(DevCtrl* c, double t0) {
   if (threadIdx.x == 0) {
     c->dt = 0.0; c->t = t0; c->t_end = 0.0; c->dt_fixed = 0.0; c->dt_last = 0.0;
     c->maxrate = 0ull; c->step = 0; c->n_fallback = 0; c->status = 0; c->fail_step = 0x7fffffff;
-    c->n_fp64 = 0; c->n_states = 0;
+    c->n_fp64 = 0; c->n_states = 0; c->n_sigma_limited = 0;
   }
 }
 
@@ -401,8 +403,32 @@ __global__ void ingest_kernel(int repr, const double* src, double* U, int nx, in
   if ((threadIdx.x & 63) == 0 && bad) atomicOr(&c->status, bad);
 }
 
+// Closing moments of a cell state (dimensional, at sigma_bar = max(sigma, sigma_lim)):
+// 14 moments: Q_ijk (10: xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz), R_ijkk (6: xx xy xz yy yz zz),
+// S_ijjkk (3: x y z); 5 moments: s.
+constexpr int NCLOSE14 = 19;
+
+MX_HD void closing14(const double* W, double sigma_lim, double* out) {
+  Sys14::Core<double> k;
+  Sys14::core(W, sigma_lim, k);
+  double Q[6], R[3], S;
+  Sys14::closure_dir<0>(k, Q, R, S);   // Q_ijx: xxx xyx xzx yyx yzx zzx
+  out[0] = Q[0]; out[1] = Q[1]; out[2] = Q[2]; out[3] = Q[3]; out[4] = Q[4]; out[5] = Q[5];
+  out[10] = R[0]; out[11] = R[1]; out[12] = R[2];
+  out[16] = S;
+  Sys14::closure_dir<1>(k, Q, R, S);   // Q_ijy: ... yyy yzy zzy
+  out[6] = Q[3]; out[7] = Q[4]; out[8] = Q[5];
+  out[13] = R[1]; out[14] = R[2];
+  out[17] = S;
+  Sys14::closure_dir<2>(k, Q, R, S);   // Q_zzz
+  out[9] = Q[5];
+  out[15] = R[2];
+  out[18] = S;
+}
+
 template <class SYS>
-__global__ void egress_kernel(int repr, const double* U, double* dst, int nx, int ny, int pitch) {
+__global__ void egress_kernel(int repr, const double* U, double* dst, int nx, int ny, int pitch,
+                              double sigma_lim) {
   constexpr int NV = SYS::NV;
   long long n = (long long)nx * ny;
   long long plane = (long long)ny * pitch;
@@ -420,11 +446,43 @@ __global__ void egress_kernel(int repr, const double* U, double* dst, int nx, in
       if (repr == 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) dst[v * n + k] = W[v];
-      } else {
+      } else if (repr == 2) {
         dst[k] = SYS::sigma(W);
+      } else if constexpr (NV == 14) {
+        double c[NCLOSE14];
+        closing14(W, sigma_lim, c);
+#pragma unroll
+        for (int m = 0; m < NCLOSE14; ++m) dst[m * n + k] = c[m];
+      } else {
+        typename SYS::template Core<double> kc;
+        SYS::core(W, sigma_lim, kc);
+        dst[k] = SYS::closing_s(kc);
       }
     }
   }
+}
+
+// cells of a state whose unlimited sigma is below sigma_lim (the closure evaluates them at
+// sigma_bar = sigma_lim), added to ctrl->n_sigma_limited
+template <class SYS>
+__global__ __launch_bounds__(256) void count_sigma_limited_kernel(const double* U, int nx, int ny,
+                                                                  int pitch, double sigma_lim,
+                                                                  DevCtrl* c) {
+  constexpr int NV = SYS::NV;
+  long long n = (long long)nx * ny;
+  long long plane = (long long)ny * pitch;
+  int cnt = 0;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+    int i = (int)(k % nx), j = (int)(k / nx);
+    double Uc[NV], W[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uc[v] = U[v * plane + (long long)j * pitch + i];
+    SYS::cons_to_prim(Uc, W);
+    cnt += (SYS::sigma(W) < sigma_lim) ? 1 : 0;
+  }
+  cnt = wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0 && cnt)
+    atomicAdd((unsigned long long*)&c->n_sigma_limited, (unsigned long long)cnt);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -452,8 +510,9 @@ static hipError_t launch_stage_p(int system, int dim, int order, const StagePara
 
 hipError_t launch_stage(int system, int dim, int order, int precision, const StageParams& p,
                         hipStream_t s) {
-  return precision == 0 ? launch_stage_p<0>(system, dim, order, p, s)
-                        : launch_stage_p<1>(system, dim, order, p, s);
+  if (precision == 1) return launch_stage_p<1>(system, dim, order, p, s);
+  if (precision == 2) return launch_stage_p<2>(system, dim, order, p, s);
+  return launch_stage_p<0>(system, dim, order, p, s);
 }
 
 hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s) {
@@ -492,12 +551,26 @@ hipError_t launch_ingest(int system, int repr, const double* src, double* U, int
 }
 
 hipError_t launch_egress(int system, int repr, const double* U, double* dst, int nx, int ny,
-                         int pitch, hipStream_t s) {
+                         int pitch, double sigma_lim, hipStream_t s) {
   long long n = (long long)nx * ny;
   int grid = (int)((n + 255) / 256);
   if (grid > 8192) grid = 8192;
-  if (system == 5) hipLaunchKernelGGL((egress_kernel<Sys5>), dim3(grid), dim3(256), 0, s, repr, U, dst, nx, ny, pitch);
-  else hipLaunchKernelGGL((egress_kernel<Sys14>), dim3(grid), dim3(256), 0, s, repr, U, dst, nx, ny, pitch);
+  if (system == 5)
+    hipLaunchKernelGGL((egress_kernel<Sys5>), dim3(grid), dim3(256), 0, s, repr, U, dst, nx, ny, pitch, sigma_lim);
+  else
+    hipLaunchKernelGGL((egress_kernel<Sys14>), dim3(grid), dim3(256), 0, s, repr, U, dst, nx, ny, pitch, sigma_lim);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_sigma_limited(int system, const double* U, int nx, int ny, int pitch,
+                                      double sigma_lim, DevCtrl* c, hipStream_t s) {
+  long long n = (long long)nx * ny;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (system == 5)
+    hipLaunchKernelGGL((count_sigma_limited_kernel<Sys5>), dim3(grid), dim3(256), 0, s, U, nx, ny, pitch, sigma_lim, c);
+  else
+    hipLaunchKernelGGL((count_sigma_limited_kernel<Sys14>), dim3(grid), dim3(256), 0, s, U, nx, ny, pitch, sigma_lim, c);
   return hipGetLastError();
 }
 

@@ -146,4 +146,19 @@ MX_HD void face_flux_mixed(const double* WL, const double* WR, double sigma_lim,
   }
 }
 
+// Single precision (the FP32 setting): the closure, wave speeds, physical fluxes and the HLL /
+// Rusanov combination of both face states in FP32, with no FP64 re-evaluation; the face
+// states arrive in FP64 and the interface flux leaves in FP64.
+template <class SYS, int D>
+MX_HD void face_flux_fp32(const double* WL, const double* WR, double sigma_lim, double kws,
+                          int flux_kind, double* Fh) {
+  constexpr int NV = SYS::NV;
+  float wl[NV], wr[NV], f[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) { wl[v] = (float)WL[v]; wr[v] = (float)WR[v]; }
+  face_flux<SYS, D, float>(wl, wr, (float)sigma_lim, (float)kws, flux_kind, f);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Fh[v] = (double)f[v];
+}
+
 }  // namespace mx

@@ -21,8 +21,9 @@ LIMITER = {'minmod': 0, 'vanalbada': 1}
 FLUX = {'hll': 0, 'rusanov': 1}
 INTEGRATOR = {'fe': 0, 'ssprk2': 1, 'midpoint': 2}
 TAU_MODE = {'local': 0, 'const': 1}
-REPR = {'primitive': 0, 'conserved': 1, 'sigma': 2}
-PRECISION = {'fp64': 0, 'mixed': 2}
+REPR = {'primitive': 0, 'conserved': 1, 'sigma': 2, 'closing': 3}
+PRECISION = {'fp64': 0, 'fp32': 1, 'mixed': 2}
+CLOSING_COMPONENTS_14 = 19
 ADJOINT_MODE = {'exact': 0, 'frozen_limiter': 1}
 
 EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_moments',
@@ -64,7 +65,8 @@ class Info(ctypes.Structure):
     _fields_ = [('t', ctypes.c_double), ('dt_last', ctypes.c_double),
                 ('steps', ctypes.c_longlong), ('n_fallback', ctypes.c_longlong),
                 ('fail_step', ctypes.c_int), ('fail_code', ctypes.c_int),
-                ('n_fp64_states', ctypes.c_longlong), ('n_face_states', ctypes.c_longlong)]
+                ('n_fp64_states', ctypes.c_longlong), ('n_face_states', ctypes.c_longlong),
+                ('n_sigma_limited', ctypes.c_longlong), ('fp64_fraction', ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -211,12 +213,16 @@ class MaxEntSolver:
         self._h = h
         self.nv = self._lib.maxent_num_vars(h)
         self.shape = (self.nv, self.problem.ny, self.problem.nx)
+        # bumped by every call that changes the state or the recorded tape, so that a
+        # reverse pass can tell whether the tape is still the one it was taken for
+        self.generation = 0
 
     def _check(self, rc):
         if rc != MAXENT_OK:
             raise MaxentError(rc, self._lib.maxent_last_error(self._h).decode())
 
     def close(self):
+        self.generation = getattr(self, 'generation', 0) + 1
         if getattr(self, '_h', None):
             self._lib.maxent_destroy(self._h)
             self._h = None
@@ -229,6 +235,7 @@ class MaxEntSolver:
 
     def init_state(self, field, repr='primitive', t0=0.0):
         torch = _torch()
+        self.generation += 1
         if isinstance(field, np.ndarray):
             a = np.ascontiguousarray(field, dtype=np.float64)
             if a.size != int(np.prod(self.shape)):
@@ -244,6 +251,7 @@ class MaxEntSolver:
         self._check(rc)
 
     def step(self, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True):
+        self.generation += 1
         info = Info()
         rc = self._lib.maxent_step(self._h, int(n), float(dt), float(tau_ref), float(t_end),
                                    ctypes.byref(info))
@@ -269,8 +277,15 @@ class MaxEntSolver:
         return info.as_dict()
 
     def get(self, repr='primitive', out=None):
+        """'primitive' | 'conserved' ([nv][ny][nx]), 'sigma' ([ny][nx]), 'closing' (closing
+        moments: [19][ny][nx] for 14 moments, [ny][nx] for 5)."""
         torch = _torch()
-        shape = self.shape if repr != 'sigma' else self.shape[1:]
+        if repr == 'sigma' or (repr == 'closing' and self.nv == 5):
+            shape = self.shape[1:]
+        elif repr == 'closing':
+            shape = (CLOSING_COMPONENTS_14,) + self.shape[1:]
+        else:
+            shape = self.shape
         if out is None:
             out = torch.empty(shape, dtype=torch.float64, device='cuda')
         self._check(self._lib.maxent_get_moments(self._h, REPR[repr], ctypes.c_void_p(out.data_ptr()), 1))
@@ -280,9 +295,11 @@ class MaxEntSolver:
     # ---------------------------------------------------------------- discrete adjoint
     def record(self, checkpoint_every, max_steps):
         """Start a tape at the current state (checkpoint_every = 0 ends it)."""
+        self.generation += 1
         self._check(self._lib.maxent_record(self._h, int(checkpoint_every), int(max_steps)))
 
     def set_inflow(self, mach, rho):
+        self.generation += 1
         self._check(self._lib.maxent_set_inflow(self._h, float(mach), float(rho)))
         self.problem.jet_mach, self.problem.jet_rho = float(mach), float(rho)
 

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.maxent_abi_version() == 2
+    assert lib.maxent_abi_version() == 3
 
 
 def test_struct_layouts_match_header():
@@ -44,7 +44,8 @@ def test_struct_layouts_match_header():
     assert S.Problem.jet_wall.offset == 216
     assert ctypes.sizeof(S.Numerics) == 5 * 4 + 4 + 3 * 8 + 4 + 4
     assert S.Numerics.source_implicit.offset == 52
-    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8
+    assert S.Info.n_sigma_limited.offset == 56 and S.Info.fp64_fraction.offset == 64
 
 
 @pytest.mark.parametrize('bad', [
@@ -104,3 +105,14 @@ def test_create_batch_rejects_bad_arguments(lib, bad):
     h = ctypes.c_void_p()
     assert lib.maxent_create_batch(ctypes.byref(p), ctypes.byref(n), 2, inst, None, ctypes.byref(h)) == -1
     assert not h.value
+
+
+def test_batch_rejects_fp32_precision(lib):
+    """FP32 face evaluation is a single-solver setting; the batch takes FP64 or MIXED."""
+    p = S.make_problem(system=14, dim=1, nx=16)
+    n = S.make_numerics(precision='fp32')
+    inst = (S.Instance * 1)()
+    inst[0].x0, inst[0].x1, inst[0].tau_ref, inst[0].t_end, inst[0].n_cells = 0.0, 1.0, 0.01, 0.1, 16
+    h = ctypes.c_void_p()
+    assert lib.maxent_create_batch(ctypes.byref(p), ctypes.byref(n), 1, inst, None, ctypes.byref(h)) == -1
+    assert b'FP64 or MIXED' in lib.maxent_last_error(None)

@@ -320,6 +320,24 @@ def test_autograd_function_matches_direct_adjoint(gpu_lib):
     s.close()
 
 
+def test_autograd_backward_refuses_a_changed_tape(gpu_lib):
+    """The backward pass reverses the solver's tape; a solver used again after the forward
+    pass (here a new initial state, which ends the tape) no longer holds that tape, and
+    backward raises."""
+    import torch
+    from paper_2401_15233_amd.autograd import MaxEntSteps
+    kw = dict(JETS, nx=16, ny=16)
+    U0 = mo.prim_to_cons14(I.crossed_jets_developed(16, 16, seed=13))
+    s = gpu_lib.MaxEntSolver(**kw)
+    U0t = torch.tensor(U0, device='cuda', requires_grad=True)
+    p = torch.tensor([3.0, 1.0, TAU_JET], dtype=torch.float64, requires_grad=True)
+    Un = MaxEntSteps.apply(U0t, p, s, 3, 0.0, 2)
+    s.init_state(np.ascontiguousarray(U0), repr='conserved')
+    with pytest.raises(RuntimeError, match='tape'):
+        Un.sum().backward()
+    s.close()
+
+
 @pytest.fixture(scope='module')
 def tangent_exe(tmp_path_factory):
     import tangent_tools as tt

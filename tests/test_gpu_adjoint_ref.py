@@ -1,0 +1,108 @@
+"""The GPU discrete adjoint (through the C-ABI) against the independent CPU reference
+gradient: reverse-mode automatic differentiation of the oracle's step transcribed into
+PyTorch (oracle/adjoint_ref.py, itself pinned to the NumPy oracle's central differences).
+
+* 64 x 64 crossed jets from rest (the adjoint workload's geometry at a reduced size), 40 CFL
+  steps recorded on the GPU (the reference replays the recorded time steps), J = dx dy sum of
+  rho u_y over x in [0.05, 0.15], y in [0.5, 1] (the upper jet's reach), both adjoint modes:
+  dJ/dM, dJ/drho_jet, dJ/dtau_ref and dJ/dU0 along a uniform scaling of the state to 1e-10
+  relative; in the frozen-limiter mode also dJ/dU0 along a seeded random direction.
+* A developed crossed-jets field (32 x 32, 10 steps, random weights), where the forward step
+  itself is ill conditioned: the same quantities (plus a beam-density direction) within
+  1e-10 relative + 2 x the reference's own change under +-4 ulp input perturbations.
+
+dJ/dU0 along a generic direction is compared in the frozen-limiter mode only: where T is
+uniform (jets and background both at T = 1) rho and P_zz are proportional, so two variables'
+limiter factors tie exactly; the exact derivative then has two one-sided values and rounding
+decides which one each implementation takes.  Directions that scale all components of a cell
+together keep such ties and are compared in both modes.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import adjoint_ref as ar, moments as mo
+from paper_2401_15233_amd import inputs as I
+from test_gpu_adjoint import JETS, TAU_JET, strip_weights, random_weights, density_direction
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+PERTURB = 4 * 2.220446049250313e-16
+
+
+def gpu_gradients(S, kw, U0, w, nsteps, K, mode):
+    s = S.MaxEntSolver(**kw)
+    s.set_adjoint_mode(mode)
+    s.init_state(np.ascontiguousarray(U0), repr='conserved')
+    s.record(K, nsteps)
+    s.step(nsteps, tau_ref=TAU_JET)
+    Un = s.get('conserved').cpu().numpy()
+    dts = s.tape()
+    gU0, g = s.adjoint(w)
+    gU0 = gU0.cpu().numpy()
+    s.close()
+    return float((w * Un).sum()), g, gU0, dts
+
+
+def compare(name, S, kw, U0, w, nsteps, K, directions, spread_trials=0):
+    """directions: {label: (v, modes)}.  With spread_trials the bar adds 2 x the reference's
+    largest change under +-4 ulp perturbations of U0."""
+    for mode in ('exact', 'frozen_limiter'):
+        frozen = mode == 'frozen_limiter'
+        J, g, gU0, dts = gpu_gradients(S, kw, U0, w, nsteps, K, mode)
+        t0 = time.perf_counter()
+        Jr, gr, gUr = ar.gradients(U0, w, dts, TAU_JET, frozen_limiter=frozen, **kw)
+        t_ref = time.perf_counter() - t0
+        dirs = {k: v for k, (v, modes) in directions.items() if mode in modes}
+        got = dict(zip(('dJ/dM', 'dJ/drho_jet', 'dJ/dtau_ref'), g))
+        ref = dict(zip(('dJ/dM', 'dJ/drho_jet', 'dJ/dtau_ref'), gr))
+        for k, v in dirs.items():
+            got['dJ/dU0 . ' + k] = float((gU0 * v).sum())
+            ref['dJ/dU0 . ' + k] = float((gUr * v).sum())
+        spread = {k: 0.0 for k in ref}
+        rng = np.random.default_rng(0)
+        for _ in range(spread_trials):
+            Up = U0 * (1.0 + rng.choice([-1.0, 1.0], U0.shape) * PERTURB)
+            _, g2, gU2 = ar.gradients(Up, w, dts, TAU_JET, frozen_limiter=frozen, **kw)
+            alt = dict(zip(('dJ/dM', 'dJ/drho_jet', 'dJ/dtau_ref'), g2))
+            for k, v in dirs.items():
+                alt['dJ/dU0 . ' + k] = float((gU2 * v).sum())
+            for k in spread:
+                spread[k] = max(spread[k], abs(alt[k] - ref[k]))
+        print(f'{name} {mode}: J gpu {J:+.15e} reference {Jr:+.15e} (reference {t_ref:.1f} s)',
+              flush=True)
+        assert abs(J - Jr) <= 1e-12 * np.abs(w).sum()
+        for k in ref:
+            rel = abs(got[k] - ref[k]) / max(abs(ref[k]), 1e-300)
+            bar = TOL * abs(ref[k]) + 2.0 * spread[k]
+            print(f'   {k}: gpu {got[k]:+.15e} reference {ref[k]:+.15e} rel {rel:.2e} '
+                  f'(bar {bar / max(abs(ref[k]), 1e-300):.2e})', flush=True)
+            assert abs(got[k] - ref[k]) <= bar, (mode, k)
+        scale = np.maximum(np.abs(gUr).reshape(14, -1).max(1), 1e-300)
+        err = np.abs(gU0 - gUr).reshape(14, -1).max(1) / scale
+        print(f'   dJ/dU0 field, per-component difference / largest value: '
+              f'{np.array2string(err, precision=1)}', flush=True)
+
+
+def test_adjoint_against_reference_gradient_crossed_jets_64(gpu_lib):
+    n = 64
+    kw = dict(JETS, nx=n, ny=n)
+    U0 = mo.prim_to_cons14(I.crossed_jets_initial(n, n))
+    w = strip_weights(n, n, 0.05, 0.15, 0.5, 1.0, 1 / n, 1 / n)
+    dirs = {'uniform scaling': (U0, ('exact', 'frozen_limiter')),
+            'random': (U0 * np.random.default_rng(3).uniform(-1, 1, U0.shape), ('frozen_limiter',))}
+    compare('64^2 crossed jets, 40 steps', gpu_lib, kw, U0, w, 40, 10, dirs)
+
+
+def test_adjoint_against_reference_gradient_developed_field(gpu_lib):
+    n = 32
+    kw = dict(JETS, nx=n, ny=n)
+    U0 = mo.prim_to_cons14(I.crossed_jets_developed(n, n, seed=21))
+    w = random_weights(n, n, 1 / n, 1 / n, seed=22)
+    Ubg = mo.prim_to_cons14(I.crossed_jets_initial(n, n))
+    dirs = {'uniform scaling': (U0, ('exact', 'frozen_limiter')),
+            'beam density': (density_direction(U0 - Ubg, seed=8), ('exact', 'frozen_limiter')),
+            'random': (U0 * np.random.default_rng(3).uniform(-1, 1, U0.shape), ('frozen_limiter',))}
+    compare('32^2 developed jets, 10 steps', gpu_lib, kw, U0, w, 10, 5, dirs, spread_trials=2)
