@@ -12,10 +12,16 @@ rho = 1e-3, T = 1; transmissive elsewhere; Kn = 0.1 through a local BGK collisio
 MUSCL-minmod, HLL, SSP-RK2, CFL 0.4, sigma_lim = 1e-4.  Inputs are synthetic (the problem
 definition itself; no dataset).
 
-Sub-records beside the headline FP64 value: the same workload in mixed precision; the
+The timed window: the run starts from rest, advances --advance (1000) steps untimed and
+--warmup more, then times --steps steps, so that the window sits in the middle of the 2000-step
+workload (where the jets are developed) rather than at its start.
+
+Sub-records beside the headline FP64 value: the same window in mixed precision; the full
+2000-step run in FP64 and mixed (average rates, FP64 re-evaluation share, L1 deviation); the
 discrete adjoint of the 512^2 jets against its forward run; 512 batched 1D shock tubes (mixed
 and FP64, autotuned launch shape); the paper's own crossed-jets geometry at 1200^2 (forward
-Euler, van Albada); and the CPU oracle on a bounded sample (skip each with its --no-* flag).
+Euler, van Albada); the two Sod workloads' time per step on the device and in the oracle; and
+the CPU oracle on a bounded sample (skip each with its --no-* flag).
 """
 import argparse
 import json
@@ -99,10 +105,37 @@ def jets_kwargs(n, k_ws=1.2):
                 jet_T=1.0)
 
 
-def cpu_baseline(n=128, steps=5):
+def host_cpu():
+    """CPU model and the number of host cores this process may run on."""
+    model = 'unknown'
+    try:
+        with open('/proc/cpuinfo') as fh:
+            for line in fh:
+                if line.startswith('model name'):
+                    model = line.split(':', 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {'cpu_model': model, 'nproc': avail}
+
+
+def _cpu_timed(fn):
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    fn()
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return wall, max(1, round(cpu / wall))
+
+
+def cpu_baseline(n=256, steps=6):
     """The oracle, as it stands, on a bounded sample of the same workload (n x n cells of
     a developed crossed-jets field, `steps` SSP-RK2 steps) on the host cores."""
-    import numpy as np
     from paper_2401_15233_amd import inputs
     from oracle import scheme as sc, moments as mo
     kw = jets_kwargs(n)
@@ -110,16 +143,32 @@ def cpu_baseline(n=128, steps=5):
                  bc=kw['bc'], jets=kw['jets'], k_ws=kw['k_ws'])
     U = mo.prim_to_cons14(inputs.crossed_jets_developed(n, n, seed=0))
     tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    sc.run(U, s, tau, nsteps=steps)
-    wall = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {'value': n * n * steps / wall, 'unit': 'cell-updates/s',
-            'cores': max(1, round(cpu / wall)), 'kind': 'oracle',
-            'sample': f'{n}x{n} developed crossed-jets field, {steps} SSP-RK2 steps, FP64 NumPy, '
-                      f'{wall:.1f} s wall'}
+    wall, cores = _cpu_timed(lambda: sc.run(U, s, tau, nsteps=steps))
+    out = {'value': n * n * steps / wall, 'unit': 'cell-updates/s', 'cores': cores, 'kind': 'oracle',
+           'sample': f'{n}x{n} developed crossed-jets field, {steps} SSP-RK2 steps, FP64 NumPy, '
+                     f'{wall:.1f} s wall'}
+    out.update(host_cpu())
+    return out
+
+
+def sod_oracle_record(steps0=2000, steps1=5):
+    """The oracle's time per step on the two Sod workloads (bounded samples): the 5-moment
+    tube (1000 cells, first order, forward Euler, Kn = 0.01), `steps0` CFL steps; the
+    14-moment tube (20000 cells, MUSCL + SSP-RK2, Kn = 0.01), `steps1` CFL steps."""
+    from paper_2401_15233_amd import inputs
+    from oracle import scheme as sc, moments as mo
+    out = {}
+    s = sc.Setup(system=5, dim=1, nx=1000, order=1, integrator='fe', cfl=0.5)
+    U = mo.prim_to_cons5(inputs.sod_prims(5, 1000))
+    wall, cores = _cpu_timed(lambda: sc.run(U, s, inputs.kn_to_tau_ref(0.01), nsteps=steps0))
+    out['sod5_1000_kn0.01'] = {'steps': steps0, 'us_per_step': 1e6 * wall / steps0, 'cores': cores,
+                               'cell_updates_per_s': 1000 * steps0 / wall}
+    s = sc.Setup(system=14, dim=1, nx=20000, order=2, integrator='ssprk2', cfl=0.5)
+    U = mo.prim_to_cons14(inputs.sod_prims(14, 20000))
+    wall, cores = _cpu_timed(lambda: sc.run(U, s, inputs.kn_to_tau_ref(0.01), nsteps=steps1))
+    out['sod14_20000_kn0.01'] = {'steps': steps1, 'us_per_step': 1e6 * wall / steps1, 'cores': cores,
+                                 'cell_updates_per_s': 20000 * steps1 / wall}
+    return out
 
 
 def adjoint_record(stream, n=512, steps=400, checkpoint_every=20):
@@ -169,10 +218,13 @@ def adjoint_record(stream, n=512, steps=400, checkpoint_every=20):
                         f'(t = {info["t"]:.4f}), checkpoint every {checkpoint_every}',
             'objective': 'dx dy sum of rho u_y over x in [0.05, 0.15], y in [0.5, 1]',
             'J': J,
-            'exact': {'dJ_dMach': g[0], 'dJ_drho_jet': g[1], 'dJ_dtau_ref': g[2],
-                      'note': 'the exact derivative of the limited scheme grows without bound '
-                              'over long horizons (it is checked on short ones)'},
-            'frozen_limiter': {'dJ_dMach': gf[0], 'dJ_drho_jet': gf[1], 'dJ_dtau_ref': gf[2]},
+            'gradient_mode': 'frozen_limiter',
+            'gradient': {'dJ_dMach': gf[0], 'dJ_drho_jet': gf[1], 'dJ_dtau_ref': gf[2]},
+            'diagnostic': {
+                'exact_mode': {'dJ_dMach': g[0], 'dJ_drho_jet': g[1], 'dJ_dtau_ref': g[2]},
+                'note': 'the exact derivative of the common-limiter scheme grows without bound '
+                        'over long horizons (the limiter\'s cross-variable gains compound); it '
+                        'matches the CPU reference gradient on short ones'},
             'forward_ms': fwd_ms, 'forward_recording_ms': rec_ms, 'adjoint_ms': adj_ms,
             'adjoint_over_forward': adj_ms / fwd_ms,
             'forward_cell_updates_per_s': n * n * steps / (fwd_ms / 1e3)}
@@ -185,8 +237,9 @@ def batch_record(stream, steps=5000, chunk=500):
     speeds inflated by k = 1.2 (with k = 1 the strongest tubes, pressure ratio > 80 and density
     ratio > 15, become unrealizable at any CFL).  Mixed precision (FP32 bulk, FP64 closure
     near the Junk subspace and the realizability boundary) is the headline form; FP64 is
-    timed beside it.  For each, the launch shape is autotuned, then `steps` steps of the whole
-    batch are timed (a bounded part of the workload: every instance is still active)."""
+    timed beside it.  For each, the launch shape is autotuned, then the first `steps` steps of
+    the whole batch are timed (a bounded prefix of the workload: tubes that reach t_end within
+    it drop out, and `active_instances_after` says how many are still running at its end)."""
     import torch
     from paper_2401_15233_amd import solver, inputs
     insts = inputs.batch_instances()
@@ -325,6 +378,95 @@ def sod_records(stream):
     return out
 
 
+def sod_gpu_record(stream, steps1=500):
+    """The device's time per step on the two Sod workloads: the 5-moment tube run in full
+    (1000 cells, first-order HLL, forward Euler, CFL 0.5, Kn = 0.01, to t = 0.2) and the first
+    `steps1` steps of the 14-moment tube (20000 cells, MUSCL-minmod + HLL + SSP-RK2, CFL 0.5,
+    Kn = 0.01).  At these sizes a step is bound by launch latency, not throughput."""
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    out = {}
+    s = solver.MaxEntSolver(system=5, dim=1, nx=1000, order=1, integrator='fe', flux='hll', cfl=0.5,
+                            stream=stream)
+    s.init_state(inputs.sod_prims(5, 1000))
+    s.step(3, tau_ref=inputs.kn_to_tau_ref(0.01))
+    s.init_state(inputs.sod_prims(5, 1000))
+    info, ms = timed(lambda: _run_to(s, 0.2, inputs.kn_to_tau_ref(0.01)))
+    s.close()
+    out['sod5_1000_kn0.01'] = {'steps': info['steps'], 'ms': ms, 'us_per_step': 1e3 * ms / info['steps'],
+                               'cell_updates_per_s': 1000 * info['steps'] / (ms / 1e3),
+                               'status': info['status'], 't': info['t']}
+    s = solver.MaxEntSolver(system=14, dim=1, nx=20000, order=2, integrator='ssprk2', flux='hll',
+                            limiter='minmod', cfl=0.5, stream=stream)
+    s.init_state(inputs.sod_prims(14, 20000))
+    s.step(3, tau_ref=inputs.kn_to_tau_ref(0.01))
+    s.init_state(inputs.sod_prims(14, 20000))
+    info, ms = timed(lambda: s.step(steps1, tau_ref=inputs.kn_to_tau_ref(0.01), check=False))
+    s.close()
+    out['sod14_20000_kn0.01'] = {'steps': info['steps'], 'ms': ms, 'us_per_step': 1e3 * ms / info['steps'],
+                                 'cell_updates_per_s': 20000 * info['steps'] / (ms / 1e3),
+                                 'status': info['status']}
+    return out
+
+
+def full_run_record(stream, n, steps=2000):
+    """The 2048^2 crossed-jets workload in full (all `steps` steps from rest, FP64 and mixed),
+    each timed with HIP events: the average rate over the whole run, the mixed form's FP64
+    re-evaluation share over it, its L1 deviation from the FP64 run at the end, and beside it
+    the FP64 run's own L1 change when its initial state carries one random FP32 rounding
+    (+-2^-24 relative), i.e. how far this flow amplifies single-precision-sized rounding."""
+    import numpy as np
+    import torch
+    from paper_2401_15233_amd import solver, inputs
+    tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
+    W0 = inputs.crossed_jets_initial(n, n)
+
+    def run(precision, init):
+        s = solver.MaxEntSolver(stream=stream, precision=precision, **jets_kwargs(n))
+        s.init_state(init)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        info = s.step(steps, tau_ref=tau, check=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        U = s.get('conserved')
+        s.close()
+        return e0.elapsed_time(e1), info, U
+
+    ms64, info64, U64 = run('fp64', W0)
+    msmx, infomx, Umx = run('mixed', W0)
+    rng = np.random.default_rng(0)
+    _, _, Up = run('fp64', W0 * (1.0 + rng.choice([-1.0, 1.0], W0.shape) * 2.0 ** -24))
+    ref = U64.abs().reshape(14, -1).sum(1).clamp_min(1e-300)
+
+    def l1(U):
+        return [float(x) for x in ((U - U64).abs().reshape(14, -1).sum(1) / ref).cpu()]
+
+    return {'workload': f'{n}x{n} crossed jets, all {steps} steps from rest',
+            'fp64': {'value': n * n * info64['steps'] / (ms64 / 1e3), 'unit': 'cell-updates/s',
+                     'ms_per_step': ms64 / max(info64['steps'], 1), 'steps': info64['steps'],
+                     'status': info64['status'], 't': info64['t']},
+            'mixed': {'value': n * n * infomx['steps'] / (msmx / 1e3), 'unit': 'cell-updates/s',
+                      'ms_per_step': msmx / max(infomx['steps'], 1), 'steps': infomx['steps'],
+                      'status': infomx['status'], 'speedup_vs_fp64': ms64 / msmx,
+                      'fp64_reevaluated_face_state_fraction': infomx['fp64_fraction'],
+                      'l1_rel_deviation_from_fp64_per_moment': l1(Umx)},
+            'fp64_l1_change_under_fp32_input_rounding_per_moment': l1(Up)}
+
+
 def paper_jets_record(stream, n=1200, steps=2000):
     """The paper's own crossed jets (Section 6): 1200^2 cells, M = 5 jets of width L/7 on the
     left and bottom walls at a right angle, background 1e-5, van Albada, HLL, forward Euler,
@@ -359,9 +501,16 @@ def paper_jets_record(stream, n=1200, steps=2000):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
-    ap.add_argument('--steps', type=int, default=2000)
-    ap.add_argument('--warmup', type=int, default=3)
+    ap.add_argument('--steps', type=int, default=20)
+    ap.add_argument('--warmup', type=int, default=5)
     ap.add_argument('--n', type=int, default=N)
+    ap.add_argument('--advance', type=int, default=1000,
+                    help='untimed steps from rest before the warm-up and the timed steps, so that '
+                         'the timed window sits in the middle of the 2000-step workload')
+    ap.add_argument('--no-full-run', action='store_true',
+                    help='skip the full 2000-step FP64 and mixed runs')
+    ap.add_argument('--no-sod', action='store_true',
+                    help='skip the Sod time-per-step records (device and oracle)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--precision', default='both', choices=('fp64', 'mixed', 'both'),
                     help='fp64 (the headline value), mixed, or both (fp64 headline plus a mixed '
@@ -408,6 +557,8 @@ def main():
         print(json.dumps({'copy_kernel_bytes_read': m * 8, 'copy_kernel_bytes_written': m * 8}))
         return
     n = a.n
+    # the timed window stays inside the 2000-step workload
+    a.advance = max(0, min(a.advance, 2000 - a.warmup - a.steps))
     tau = inputs.kn_to_tau_ref(0.1, L_ref=0.1)
     stream = torch.cuda.current_stream()
     W0 = inputs.crossed_jets_initial(n, n)
@@ -417,6 +568,8 @@ def main():
         kw['precision'] = precision
         s = solver.MaxEntSolver(stream=stream, **kw)
         s.init_state(W0 if init is None else init)
+        if a.advance:
+            s.step(a.advance, tau_ref=tau)
         if a.warmup:
             s.step(a.warmup, tau_ref=tau)
         s.set_profiling(True)
@@ -460,7 +613,9 @@ def main():
         'config': {'workload': f'2D crossed jets, 14-moment, {n}x{n}, MUSCL-minmod + HLL + '
                                f'SSP-RK2, CFL 0.4, Kn 0.1, wave speeds x 1.2', 'cells': cells,
                    'precision': 'fp64',
-                   'steps_in_workload': 2000, 'precision_mode': head},
+                   'steps_in_workload': 2000, 'precision_mode': head,
+                   'timed_window': f'steps {a.advance + a.warmup + 1}..{a.advance + a.warmup + a.steps} '
+                                   f'of the run from rest'},
         'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms / 1e3) / 1e9,
         'sim_time_reached': info['t'],
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VECTOR_PEAK_TFLOPS,
@@ -501,12 +656,18 @@ def main():
             'fp64_reevaluated_face_state_fraction':
                 info_m['n_fp64_states'] / max(info_m['n_face_states'], 1),
         }
+    if not a.no_full_run:
+        out['full_run'] = full_run_record(stream, n)
     if not a.no_adjoint:
         out['adjoint'] = adjoint_record(stream)
     if not a.no_batch:
         out['batched'] = batch_record(stream)
     if not a.no_paper_jets:
         out['paper_jets'] = paper_jets_record(stream)
+    if not a.no_sod:
+        out['sod'] = {'gpu': sod_gpu_record(stream)}
+        if not a.no_cpu_baseline:
+            out['sod']['oracle'] = sod_oracle_record()
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -92,10 +92,16 @@ struct maxent_solver {
   std::string err;
 };
 
-static std::string g_create_err;
+// message of the last failed call without a handle (maxent_create, maxent_create_batch); a
+// fixed buffer, so that reporting needs no host allocation
+static char g_create_err[512] = "";
+
+static void set_create_err(const char* msg) {
+  std::snprintf(g_create_err, sizeof(g_create_err), "%s", msg);
+}
 
 static int fail(maxent_solver* s, int code, const std::string& msg) {
-  if (s) s->err = msg; else g_create_err = msg;
+  if (s) s->err = msg; else set_create_err(msg.c_str());
   // a failed runtime call (e.g. an allocation beyond the card's memory) leaves its error as the
   // runtime's last error, which the next launch check would report: the error is reported
   // here, so clear it
@@ -110,7 +116,8 @@ static int fail(maxent_solver* s, int code, const std::string& msg) {
       return fail((s), MAXENT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
+// "" when the problem and numerics are consistent, else what is wrong (a literal)
+static const char* validate(const maxent_problem& p, const maxent_numerics& n) {
   if (p.system != 5 && p.system != 14) return "system must be 5 or 14";
   if (p.dim != 1 && p.dim != 2) return "dim must be 1 or 2";
   if (p.system == 5 && p.dim != 1) return "the 5-moment system is one-dimensional";
@@ -164,7 +171,7 @@ static std::string validate(const maxent_problem& p, const maxent_numerics& n) {
 extern "C" int maxent_abi_version(void) { return MAXENT_ABI_VERSION; }
 
 extern "C" const char* maxent_last_error(const maxent_solver* s) {
-  return s ? s->err.c_str() : g_create_err.c_str();
+  return s ? s->err.c_str() : g_create_err;
 }
 
 extern "C" int maxent_num_vars(const maxent_solver* s) { return s ? s->nv : 0; }
@@ -442,6 +449,54 @@ extern "C" int maxent_init_state(maxent_solver* s, int repr, const double* src, 
   return MAXENT_OK;
 }
 
+// Enqueue n steps on the solver's stream (no host synchronisation, no allocation): the
+// control block sets dt (fixed or CFL) and t_end; each step is the finalize kernel, then one
+// stage kernel (FE) or two (SSP-RK2, midpoint); with a tape, each step's dt and tau_ref are
+// kept and a checkpoint every K steps.  FE ping-pongs between U and Us (the pointers swap).
+static hipError_t enqueue_steps(maxent_solver* s, int n, double dt, double tau_ref, double t_end) {
+  TapeState* tape = s->tape;
+  const size_t field_bytes = (size_t)s->nv * s->plane * sizeof(double);
+  const bool cfl_mode = !(dt > 0);
+  mx::StageParams p = stage_params(s, tau_ref);
+  const int sys = s->prob.system, dim = s->prob.dim, ord = s->num.order;
+  const double dx = (s->prob.x1 - s->prob.x0) / s->prob.nx;
+  hipError_t e = mx::launch_ctrl_set(s->ctrl, cfl_mode ? 0.0 : dt, t_end > 0 ? t_end : 0.0, s->stream);
+  if (e != hipSuccess) return e;
+  if (cfl_mode && !s->rate_valid && (e = run_cfl(s)) != hipSuccess) return e;
+  for (int k = 0; k < n; ++k) {
+    if ((e = mx::launch_finalize(s->ctrl, dim, s->num.cfl, dx, s->stream)) != hipSuccess) return e;
+    if (tape) {
+      if ((e = mx::launch_tape_dt(s->ctrl, tape->d_dt + tape->n, s->stream)) != hipSuccess) return e;
+      tape->tau.push_back(tau_ref);   // capacity reserved by maxent_record
+    }
+    if (s->num.integrator == MAXENT_FE) {
+      p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
+      p.mode = mx::MODE_EULER; p.cdt = 1.0; p.do_cfl = cfl_mode; p.copy_on_idle = 1;
+      if ((e = stage(s, sys, dim, ord, p)) != hipSuccess) return e;
+      // the result lives in Us; swap so that U is always the current state
+      double* tmp = s->U; s->U = s->Us; s->Us = tmp;
+    } else {
+      p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
+      p.mode = mx::MODE_EULER;
+      p.copy_on_idle = 0;
+      p.cdt = (s->num.integrator == MAXENT_MIDPOINT) ? 0.5 : 1.0;
+      p.do_cfl = 0;
+      if ((e = stage(s, sys, dim, ord, p)) != hipSuccess) return e;
+      p.Ub = s->Us; p.Ua = s->U; p.Uout = s->U;
+      p.mode = (s->num.integrator == MAXENT_MIDPOINT) ? mx::MODE_MID2 : mx::MODE_HEUN2;
+      p.cdt = 1.0;
+      p.do_cfl = cfl_mode;
+      if ((e = stage(s, sys, dim, ord, p)) != hipSuccess) return e;
+    }
+    if (tape && ++tape->n % tape->K == 0) {
+      e = hipMemcpyAsync(tape->ckpt[tape->n / tape->K], s->U, field_bytes, hipMemcpyDeviceToDevice,
+                         s->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
 extern "C" int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, double t_end,
                            maxent_info* info) {
   if (!s) return MAXENT_E_INVAL;
@@ -454,45 +509,8 @@ extern "C" int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, d
   TapeState* tape = s->tape;
   if (tape && tape->n + n > tape->max_steps)
     return fail(s, MAXENT_E_INVAL, "the tape would exceed its max_steps");
-  const size_t field_bytes = (size_t)s->nv * s->plane * sizeof(double);
   const bool cfl_mode = !(dt > 0);
-  mx::StageParams p = stage_params(s, tau_ref);
-  const int sys = s->prob.system, dim = s->prob.dim, ord = s->num.order;
-  const double dx = (s->prob.x1 - s->prob.x0) / s->prob.nx;
-  HIP_TRY(s, mx::launch_ctrl_set(s->ctrl, cfl_mode ? 0.0 : dt, t_end > 0 ? t_end : 0.0, s->stream));
-  if (cfl_mode && !s->rate_valid) HIP_TRY(s, run_cfl(s));
-  for (int k = 0; k < n; ++k) {
-    HIP_TRY(s, mx::launch_finalize(s->ctrl, dim, s->num.cfl, dx, s->stream));
-    if (tape) {
-      HIP_TRY(s, mx::launch_tape_dt(s->ctrl, tape->d_dt + tape->n, s->stream));
-      tape->tau.push_back(tau_ref);
-    }
-    if (s->num.integrator == MAXENT_FE) {
-      p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
-      p.mode = mx::MODE_EULER; p.cdt = 1.0; p.do_cfl = cfl_mode; p.copy_on_idle = 1;
-      HIP_TRY(s, stage(s, sys, dim, ord, p));
-      // the result lives in Us; swap so that U is always the current state
-      double* tmp = s->U; s->U = s->Us; s->Us = tmp;
-      if (tape && ++tape->n % tape->K == 0)
-        HIP_TRY(s, hipMemcpyAsync(tape->ckpt[tape->n / tape->K], s->U, field_bytes,
-                                  hipMemcpyDeviceToDevice, s->stream));
-      continue;
-    }
-    p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
-    p.mode = mx::MODE_EULER;
-    p.copy_on_idle = 0;
-    p.cdt = (s->num.integrator == MAXENT_MIDPOINT) ? 0.5 : 1.0;
-    p.do_cfl = 0;
-    HIP_TRY(s, stage(s, sys, dim, ord, p));
-    p.Ub = s->Us; p.Ua = s->U; p.Uout = s->U;
-    p.mode = (s->num.integrator == MAXENT_MIDPOINT) ? mx::MODE_MID2 : mx::MODE_HEUN2;
-    p.cdt = 1.0;
-    p.do_cfl = cfl_mode;
-    HIP_TRY(s, stage(s, sys, dim, ord, p));
-    if (tape && ++tape->n % tape->K == 0)
-      HIP_TRY(s, hipMemcpyAsync(tape->ckpt[tape->n / tape->K], s->U, field_bytes,
-                                hipMemcpyDeviceToDevice, s->stream));
-  }
+  HIP_TRY(s, enqueue_steps(s, n, dt, tau_ref, t_end));
   int rc = read_ctrl(s);
   if (rc) return rc;
   if (s->prof) HIP_TRY(s, collect_profile(s));

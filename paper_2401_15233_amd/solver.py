@@ -195,6 +195,10 @@ class MaxEntSolver:
     Fields are [nv][ny][nx] float64 (torch CUDA tensors or NumPy arrays on input; torch CUDA
     tensors on output)."""
 
+    # bumped by every call that changes the state or the recorded tape, so that a reverse
+    # pass can tell whether the tape is still the one it was taken for
+    generation = 0
+
     def __init__(self, stream=None, **kw):
         self._lib = load_library()
         torch = _torch()
@@ -213,16 +217,13 @@ class MaxEntSolver:
         self._h = h
         self.nv = self._lib.maxent_num_vars(h)
         self.shape = (self.nv, self.problem.ny, self.problem.nx)
-        # bumped by every call that changes the state or the recorded tape, so that a
-        # reverse pass can tell whether the tape is still the one it was taken for
-        self.generation = 0
 
     def _check(self, rc):
         if rc != MAXENT_OK:
             raise MaxentError(rc, self._lib.maxent_last_error(self._h).decode())
 
     def close(self):
-        self.generation = getattr(self, 'generation', 0) + 1
+        self.generation += 1
         if getattr(self, '_h', None):
             self._lib.maxent_destroy(self._h)
             self._h = None
