@@ -316,6 +316,32 @@ int maxent_set_adjoint_mode(maxent_solver* s, int mode);
 int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ_on_device, double* dJ_dU0,
                         int dU0_on_device, double* dJ_dparams);
 
+/* ------------------------------------------------------------------ no-allocation stepping
+ * For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * allocation): the work of maxent_create + maxent_init_state(CONSERVED) + maxent_step with
+ * no handle and no allocation of any kind.  The intermediate stage state and the control block
+ * live in a fixed device array of MAXENT_NOALLOC_SCRATCH_BYTES inside the library (one per
+ * device, held until the process ends), so a problem fits when
+ *   256 + 8 * nv * nx * ny <= MAXENT_NOALLOC_SCRATCH_BYTES
+ * (at most 599 184 cells with 14 moments, e.g. 768 x 768; 1 677 715 cells with 5); larger
+ * problems are rejected with INVAL before any device work.
+ *   U        the caller's device state, conserved, [nv][ny][nx] unpadded (the field-array
+ *            layout above); read as the state at t0, overwritten with the state after the
+ *            steps.  Checked first: a non-finite or unrealizable input returns NONFINITE /
+ *            UNREALIZABLE with fail_step = 0 and no step taken.
+ *   n, dt, tau_ref, t_end   as for maxent_step; t0 the time of the input state.
+ *   stream   hipStream_t (NULL: default stream); the call synchronises it once at the end.
+ *   info     optional report as for maxent_step (n_sigma_limited = -1).
+ * The results equal those of maxent_create / maxent_init_state / maxent_step on the same
+ * state (the same kernels).  Every call on one device shares that device's scratch: calls
+ * that overlap on one device (other host threads, other streams) race and must be
+ * serialised by the caller.  Errors (message in maxent_last_error(NULL)): INVAL (bad
+ * arguments, problem too large), NONFINITE, UNREALIZABLE (info->fail_step), DEVICE. */
+#define MAXENT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int maxent_step_noalloc(const maxent_problem* problem, const maxent_numerics* numerics,
+                        double* U, int n, double dt, double tau_ref, double t_end, double t0,
+                        void* stream, maxent_info* info);
+
 /* Optional timing of the fused stage kernels: when enabled, every stage-kernel launch of
  * maxent_step is bracketed by HIP events on the solver's stream and the elapsed times are
  * accumulated (read at the end of each maxent_step call).  Enabling resets the totals. */

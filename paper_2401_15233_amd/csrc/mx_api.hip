@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -92,8 +93,8 @@ struct maxent_solver {
   std::string err;
 };
 
-// message of the last failed call without a handle (maxent_create, maxent_create_batch); a
-// fixed buffer, so that reporting needs no host allocation
+// message of the last failed call without a handle (maxent_create, maxent_create_batch,
+// maxent_step_noalloc); a fixed buffer, so that reporting needs no host allocation
 static char g_create_err[512] = "";
 
 static void set_create_err(const char* msg) {
@@ -520,6 +521,105 @@ extern "C" int maxent_step(maxent_solver* s, int n, double dt, double tau_ref, d
   if (st && tape) tape->failed = true;
   if (st & mx::ST_NONFINITE) return fail(s, MAXENT_E_NONFINITE, "non-finite cell state");
   if (st & mx::ST_UNREALIZABLE) return fail(s, MAXENT_E_UNREALIZABLE, "rho <= 0 or P not SPD at a cell");
+  return MAXENT_OK;
+}
+
+// ------------------------------------------------------------------ no-allocation stepping
+// Device scratch of maxent_step_noalloc: the control block, then one intermediate state.  Each
+// device holds its own copy of this array once the library's code runs on it; host code uses
+// the per-device address from hipGetSymbolAddress, never the array's name.
+static __device__ __align__(256) unsigned char scratch[MAXENT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+static int noalloc_fail(int code, const char* what, hipError_t e = hipSuccess) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    std::snprintf(g_create_err, sizeof(g_create_err), "%s: %s", what, hipGetErrorString(e));
+  } else {
+    set_create_err(what);
+  }
+  return code;
+}
+
+extern "C" int maxent_step_noalloc(const maxent_problem* problem, const maxent_numerics* numerics,
+                                   double* U, int n, double dt, double tau_ref, double t_end,
+                                   double t0, void* stream, maxent_info* info) {
+  if (!problem || !numerics || !U) return noalloc_fail(MAXENT_E_INVAL, "null argument");
+  if (n < 0) return noalloc_fail(MAXENT_E_INVAL, "n must be >= 0");
+  if (!std::isfinite(dt) || std::isnan(tau_ref) || std::isnan(t_end) || !std::isfinite(t0))
+    return noalloc_fail(MAXENT_E_INVAL, "dt and t0 must be finite, tau_ref and t_end not NaN");
+  const char* why = validate(*problem, *numerics);
+  if (*why) return noalloc_fail(MAXENT_E_INVAL, why);
+  const int nv = problem->system;
+  const long long cells = (long long)problem->nx * problem->ny;
+  const long long need = 256 + (long long)nv * cells * (long long)sizeof(double);
+  if (need > (long long)MAXENT_NOALLOC_SCRATCH_BYTES)
+    return noalloc_fail(MAXENT_E_INVAL, "problem too large for the no-allocation scratch "
+                                        "(nv * nx * ny * 8 + 256 bytes must not exceed "
+                                        "MAXENT_NOALLOC_SCRATCH_BYTES)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return noalloc_fail(MAXENT_E_DEVICE, "hipGetDevice", e);
+  if (dev < 0 || dev >= MAX_DEVICES) return noalloc_fail(MAXENT_E_DEVICE, "device index out of range");
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) return noalloc_fail(MAXENT_E_DEVICE, "hipGetSymbolAddress(scratch)", e);
+      g_scratch_ptr[dev] = ptr;
+    }
+    base = g_scratch_ptr[dev];
+  }
+  // a handle on the stack over the caller's state (pitch = nx: the caller's unpadded layout)
+  // and the scratch; it owns nothing, and nothing below allocates
+  maxent_solver t;
+  t.prob = *problem;
+  t.num = *numerics;
+  if (t.prob.dim == 1) { t.prob.bc[2] = t.prob.bc[3] = MAXENT_BC_TRANSMISSIVE; }
+  t.stream = (hipStream_t)stream;
+  t.device = dev;
+  t.nv = nv;
+  t.pitch = problem->nx;
+  t.plane = (long long)problem->ny * problem->nx;
+  t.ctrl = (DevCtrl*)base;
+  t.U = U;
+  t.Us = (double*)((unsigned char*)base + 256);
+  t.rate_valid = false;
+  static_assert(sizeof(DevCtrl) <= 256, "the control block fits its scratch slot");
+  // the control block starts from zero (a kernel, not a memset); the input state is checked
+  // in place (conserved in, the same values out) and its first CFL rate reduced
+  e = mx::launch_ctrl_reset(t.ctrl, t0, t.stream);
+  if (e == hipSuccess)
+    e = mx::launch_ingest(nv, MAXENT_CONSERVED, U, U, problem->nx, problem->ny, problem->nx, t.ctrl, t.stream);
+  if (e == hipSuccess) e = enqueue_steps(&t, n, dt, tau_ref, t_end);
+  // FE ping-pongs: after an odd number of steps the state sits in the scratch
+  if (e == hipSuccess && t.U != U)
+    e = hipMemcpyAsync(U, t.U, (size_t)nv * cells * sizeof(double), hipMemcpyDeviceToDevice, t.stream);
+  DevCtrl host;
+  if (e == hipSuccess) e = hipMemcpyAsync(&host, t.ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, t.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(t.stream);
+  if (e != hipSuccess) return noalloc_fail(MAXENT_E_DEVICE, "maxent_step_noalloc", e);
+  if (info) {
+    info->t = host.t;
+    info->dt_last = host.dt_last;
+    info->steps = host.step;
+    info->n_fallback = host.n_fallback;
+    info->fail_step = (host.fail_step == 0x7fffffff) ? 0 : host.fail_step;
+    info->fail_code = host.status;
+    info->n_fp64_states = host.n_fp64;
+    info->n_face_states = host.n_states;
+    info->n_sigma_limited = -1;
+    info->fp64_fraction = host.n_states > 0 ? (double)host.n_fp64 / (double)host.n_states
+                                            : (numerics->precision == MAXENT_FP64 ? 1.0 : 0.0);
+  }
+  if (host.status & mx::ST_NONFINITE) return noalloc_fail(MAXENT_E_NONFINITE, "non-finite cell state");
+  if (host.status & mx::ST_UNREALIZABLE)
+    return noalloc_fail(MAXENT_E_UNREALIZABLE, "rho <= 0 or P not SPD at a cell");
   return MAXENT_OK;
 }
 

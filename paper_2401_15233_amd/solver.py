@@ -32,7 +32,7 @@ EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_mom
             'maxent_create_batch', 'maxent_step_batch', 'maxent_set_batch_launch',
             'maxent_get_batch_launch', 'maxent_autotune_batch', 'maxent_record',
             'maxent_set_inflow', 'maxent_step_adjoint', 'maxent_tape_info',
-            'maxent_set_adjoint_mode')
+            'maxent_set_adjoint_mode', 'maxent_step_noalloc')
 
 
 class MaxentError(RuntimeError):
@@ -138,6 +138,9 @@ def load_library(path=LIB_PATH):
     L.maxent_set_adjoint_mode.argtypes = [vp, ctypes.c_int]
     L.maxent_step_adjoint.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_double)]
+    L.maxent_step_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Numerics), vp,
+                                      ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(Info)]
     _lib = L
     return L
 

@@ -1,0 +1,96 @@
+"""maxent_step_noalloc (steps on the caller's device state with the library's fixed device
+scratch, no allocation) against the handle-based path (maxent_create / maxent_init_state /
+maxent_step / maxent_get_moments) on the same states: the same kernels, so the results
+agree bit for bit.  Two calls in a row, the second on a smaller problem (the shared scratch
+keeps the first call's contents, which must not leak into the second), an FE run with an
+odd step count (its result is copied back from the scratch), a problem too large for the
+scratch (INVAL before any device work) and an unrealizable input (UNREALIZABLE, step 0)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2401_15233_amd import inputs as I
+from oracle import moments as mo
+
+pytestmark = pytest.mark.gpu
+
+JETS = dict(system=14, dim=2, order=2, integrator='ssprk2', flux='hll', cfl=0.4,
+            limiter='minmod', bc=('jet', 'transmissive', 'transmissive', 'transmissive'),
+            jets=[(0.35, 0.1, 30.0), (0.65, 0.1, -30.0)], jet_mach=3.0, jet_rho=1.0, jet_T=1.0)
+TAU = I.kn_to_tau_ref(0.1, L_ref=0.1)
+
+
+def split(kw):
+    from paper_2401_15233_amd import solver as S
+    pk = {k: v for k, v in kw.items() if k in S._PROBLEM_KEYS}
+    nk = {k: v for k, v in kw.items() if k not in S._PROBLEM_KEYS}
+    return S.make_problem(**pk), S.make_numerics(**nk)
+
+
+def noalloc(S, kw, U0, n, dt=0.0, tau_ref=TAU, t_end=0.0):
+    import torch
+    prob, num = split(kw)
+    U = torch.tensor(np.ascontiguousarray(U0), dtype=torch.float64, device='cuda')
+    info = S.Info()
+    stream = torch.cuda.current_stream()
+    L = S.load_library()
+    rc = L.maxent_step_noalloc(ctypes.byref(prob), ctypes.byref(num), ctypes.c_void_p(U.data_ptr()),
+                               int(n), float(dt), float(tau_ref), float(t_end), 0.0,
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(info))
+    return rc, U.cpu().numpy(), info.as_dict()
+
+
+def handle(S, kw, U0, n, dt=0.0, tau_ref=TAU, t_end=0.0):
+    s = S.MaxEntSolver(**kw)
+    s.init_state(np.ascontiguousarray(U0), repr='conserved')
+    info = s.step(n, dt=dt, tau_ref=tau_ref, t_end=t_end)
+    U = s.get('conserved').cpu().numpy()
+    s.close()
+    return U, info
+
+
+def check_same(S, kw, U0, n, **k):
+    rc, Un, info = noalloc(S, kw, U0, n, **k)
+    Uh, ih = handle(S, kw, U0, n, **k)
+    assert rc == 0, S.load_library().maxent_last_error(None)
+    assert info['steps'] == ih['steps'] and info['t'] == ih['t'] and info['dt_last'] == ih['dt_last']
+    assert np.array_equal(Un, Uh)
+    return info
+
+
+def test_two_calls_in_a_row_second_smaller(gpu_lib):
+    big = dict(JETS, nx=96, ny=90)
+    small = dict(JETS, nx=40, ny=36)
+    i1 = check_same(gpu_lib, big, mo.prim_to_cons14(I.crossed_jets_developed(96, 90, seed=3)), 4)
+    i2 = check_same(gpu_lib, small, mo.prim_to_cons14(I.crossed_jets_developed(40, 36, seed=4)), 3)
+    assert i1['steps'] == 4 and i2['steps'] == 3
+
+
+def test_forward_euler_odd_steps_and_fixed_dt(gpu_lib):
+    kw = dict(system=14, dim=1, nx=300, order=2, integrator='fe', flux='hll', cfl=0.5, limiter='minmod',
+              bc=('transmissive',) * 4)
+    U0 = mo.prim_to_cons14(I.sod_prims(14, 300)).reshape(14, 1, 300)
+    check_same(gpu_lib, kw, U0, 7, tau_ref=0.01)
+    check_same(gpu_lib, kw, U0, 4, dt=2e-4, tau_ref=0.01, t_end=5e-4)
+    kw5 = dict(system=5, dim=1, nx=1000, order=1, integrator='fe', flux='hll', cfl=0.5)
+    check_same(gpu_lib, kw5, mo.prim_to_cons5(I.sod_prims(5, 1000)).reshape(5, 1, 1000), 5, tau_ref=0.01)
+
+
+def test_too_large_and_unrealizable_inputs(gpu_lib):
+    import torch
+    L = gpu_lib.load_library()
+    kw = dict(JETS, nx=800, ny=800)          # 640 000 cells > 599 184
+    rc, _, _ = noalloc(gpu_lib, dict(JETS, nx=8, ny=8), np.zeros((14, 8, 8)), 0)
+    assert rc == -5                           # rho = 0: unrealizable input, fail step 0
+    prob, num = split(kw)
+    info = gpu_lib.Info()
+    buf = torch.zeros(16, dtype=torch.float64, device='cuda')   # never touched: rejected first
+    rc = L.maxent_step_noalloc(ctypes.byref(prob), ctypes.byref(num), ctypes.c_void_p(buf.data_ptr()),
+                               1, 0.0, TAU, 0.0, 0.0, None, ctypes.byref(info))
+    assert rc == -1 and b'too large' in L.maxent_last_error(None)
+    U0 = mo.prim_to_cons14(I.crossed_jets_initial(16, 16))
+    U0[0, 3, 4] = -1.0
+    rc, Un, info = noalloc(gpu_lib, dict(JETS, nx=16, ny=16), U0, 3)
+    assert rc == -5 and info['steps'] == 0 and info['fail_step'] == 0
+    assert np.array_equal(Un, U0)
