@@ -43,7 +43,7 @@ BYTES_PER_CELL_STAGE = {1: 224.0, 2: 336.0}
 # redundancy; add/sub/mul = 1, fma = 2, div/sqrt/exp/log = 1), counted by running the
 # library's own templated device code with a counting scalar:
 # paper_2401_15233_amd/csrc/flopcount.cpp (tests/test_flopcount.py keeps these in sync)
-FLOPS_PER_CELL_STAGE = {1: 4791, 2: 5074}
+FLOPS_PER_CELL_STAGE = {1: 4080, 2: 4426}
 SOURCES_FOR_TRAFFIC = ('paper_2401_15233_amd/csrc/mx_kernels.hip',
                        'paper_2401_15233_amd/csrc/mx_physics.hpp',
                        'paper_2401_15233_amd/csrc/mx_scheme.hpp',

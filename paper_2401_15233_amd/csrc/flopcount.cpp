@@ -71,17 +71,14 @@ static void cell_stage(bool last) {
   CD W[5][14], U[14], Wc[14];
   for (int k = 0; k < 5; ++k) state(k - 2.0, W[k]);
   Sys14::prim_to_cons(W[2], U);
-  // primitive recovery of the stage input (once per cell)
+  // primitive recovery of the stage input (once per cell: the update takes the centre's
+  // primitives from the loaded tile)
   Sys14::cons_to_prim(U, Wc);
   CD sl(1e-4), kws(1.0);
   for (int d = 0; d < 2; ++d) {
     // common limiter factor and the positivity check of the cell's two face states
     CD phi = mx::limiter_factor<Sys14>(W[1], W[2], W[3], 0);
-    CD Wf[14];
-    mx::face_state<Sys14>(W[1], W[2], W[3], phi, CD(1.0), Wf);
-    (void)Sys14::admissible(Wf);
-    mx::face_state<Sys14>(W[1], W[2], W[3], phi, CD(-1.0), Wf);
-    (void)Sys14::admissible(Wf);
+    (void)mx::faces_admissible<Sys14>(W[1], W[2], W[3], phi);
     // the cell's own face along d: left state from this cell, right state from the next
     CD WL[14], WR[14], Fh[14];
     mx::face_state<Sys14>(W[1], W[2], W[3], phi, CD(1.0), WL);
@@ -101,11 +98,14 @@ static void cell_stage(bool last) {
     L = L + C[v];
     Un[v] = CD(0.5) * U[v] + CD(0.5) * (U[v] + CD(1e-5) * L);
   }
-  Sys14::cons_to_prim(Un, Wn);
-  (void)Sys14::admissible(Wn);
   if (last) {
+    // the last stage: the new state's primitives give the check and the next CFL rate
+    Sys14::cons_to_prim(Un, Wn);
+    (void)Sys14::admissible(Wn);
     CD r = Sys14::cell_rate2d(Wn, sl, kws, CD(1.0 / 2048), CD(1.0 / 2048));
     (void)r;
+  } else {
+    (void)Sys14::admissible_cons(Un);
   }
 }
 

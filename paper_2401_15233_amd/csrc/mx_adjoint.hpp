@@ -1100,12 +1100,7 @@ struct Adj14 {
     }
     T phi = (den == T(1)) ? num : mdiv(num, den);
     if (fallback && phi > T(0)) {
-      T Wf[NV];
-      face_state<S>(Wm, Wc, Wp, phi, T(1), Wf);
-      bool ok = S::admissible(Wf);
-      face_state<S>(Wm, Wc, Wp, phi, T(-1), Wf);
-      ok = ok && S::admissible(Wf);
-      if (!ok) { phi = T(0); vstar = -1; }
+      if (!faces_admissible<S>(Wm, Wc, Wp, phi)) { phi = T(0); vstar = -1; }
     }
     return phi;
   }

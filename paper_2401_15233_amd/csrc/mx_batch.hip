@@ -219,11 +219,7 @@ void batch_stage_kernel(BatchParams p) {
         lds(ti - 1, Wm); lds(ti, Wc); lds(ti + 1, Wp);
         double phi = limiter_factor<SYS>(Wm, Wc, Wp, p.limiter);
         if (p.fallback && phi > 0.0) {
-          double Wf[NV];
-          face_state<SYS>(Wm, Wc, Wp, phi, 1.0, Wf);
-          bool ok = SYS::admissible(Wf);
-          face_state<SYS>(Wm, Wc, Wp, phi, -1.0, Wf);
-          ok = ok && SYS::admissible(Wf);
+          const bool ok = faces_admissible<SYS>(Wm, Wc, Wp, phi);
           if (!ok) {
             phi = 0.0;
             if (ti >= 0 && ti < TX && i0 + ti < n) ++nfb;
@@ -289,11 +285,16 @@ void batch_stage_kernel(BatchParams p) {
       bool fin = true;
 #pragma unroll
       for (int v = 0; v < NV; ++v) fin = fin && isfinite(Un[v]);
-      double Wn[NV];
-      SYS::cons_to_prim(Un, Wn);
-      if (!fin) flag |= ST_NONFINITE;
-      else if (!SYS::admissible(Wn)) flag |= ST_UNREALIZABLE;
-      else if (p.do_cfl) rate = fmax(rate, SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws));
+      if (!fin) {
+        flag |= ST_NONFINITE;
+      } else if (p.do_cfl) {
+        double Wn[NV];
+        SYS::cons_to_prim(Un, Wn);
+        if (!SYS::admissible(Wn)) flag |= ST_UNREALIZABLE;
+        else rate = fmax(rate, SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws));
+      } else if (!SYS::admissible_cons(Un)) {
+        flag |= ST_UNREALIZABLE;
+      }
     }
     flag = bwave_or(flag);
     nfb = bwave_sum(nfb);

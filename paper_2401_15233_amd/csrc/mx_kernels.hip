@@ -117,17 +117,10 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       double Wm[NV], Wc[NV], Wp[NV];
       lds(ti - di, tj - dj, Wm); lds(ti, tj, Wc); lds(ti + di, tj + dj, Wp);
       double phi = limiter_factor<SYS>(Wm, Wc, Wp, p.limiter);
-      if (p.fallback && phi > 0.0) {
-        double Wf[NV];
-        face_state<SYS>(Wm, Wc, Wp, phi, 1.0, Wf);
-        bool ok = SYS::admissible(Wf);
-        face_state<SYS>(Wm, Wc, Wp, phi, -1.0, Wf);
-        ok = ok && SYS::admissible(Wf);
-        if (!ok) {
-          phi = 0.0;
-          const bool own = isx ? (ti >= 0 && ti < TX) : (tj >= 0 && tj < TY);
-          if (own && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
-        }
+      if (p.fallback && phi > 0.0 && !faces_admissible<SYS>(Wm, Wc, Wp, phi)) {
+        phi = 0.0;
+        const bool own = isx ? (ti >= 0 && ti < TX) : (tj >= 0 && tj < TY);
+        if (own && i0 + ti < p.nx && j0 + tj < p.ny) ++nfb;
       }
       if (isx) sPx[c] = phi;
       else sPy[c - NPX] = phi;
@@ -180,6 +173,34 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       nstates += 2;
     }
   }
+  // 3c. the update's inputs, gathered before the barriers so that the global loads overlap
+  // the waits: the cell's stage input and (second-stage combinations) U^n from memory, its
+  // primitives from the tile in LDS (converted by the load phase, so no second primitive
+  // recovery) and the BGK source at the cell centre
+  const int ci = t % TX, cj = t / TX;
+  const bool own = (t < TX * TY) && (i0 + ci < p.nx) && (j0 + cj < p.ny);
+  const long long off = (long long)(j0 + cj) * p.pitch + (i0 + ci);
+  const bool implicit_src = p.use_source && p.src_implicit;
+  double Ub[NV], Ua[NV], Cs[NV];
+  if (own) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + off];
+    if (p.mode != MODE_EULER) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Ua[v] = p.Ua[v * p.plane + off];
+    }
+    if (p.use_source && !implicit_src) {
+      double W[NV];
+      lds(ci, cj, W);
+      const double rho = W[0];
+      const double T = SYS::pressure(W) / rho;
+      const double tau = (p.tau_mode == 0) ? p.tau_ref * (p.rho_ref / rho) * sqrt(p.T_ref / T) : p.tau_ref;
+      SYS::source(W, 1.0 / tau, Cs);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Cs[v] = 0.0;
+    }
+  }
   __syncthreads();
   if constexpr (DIM == 2) {
     if (has_y) {
@@ -192,26 +213,8 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   // 4. update
   int flag = 0;
   double rate = 0.0;
-  if (t < TX * TY) {
-    int ci = t % TX, cj = t / TX;
-    int gi = i0 + ci, gj = j0 + cj;
-    if (gi < p.nx && gj < p.ny) {
-      long long off = (long long)gj * p.pitch + gi;
-      double Ub[NV], W[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + off];
-      SYS::cons_to_prim(Ub, W);
-      double Cs[NV];
-      const bool implicit_src = p.use_source && p.src_implicit;
-      if (p.use_source && !implicit_src) {
-        double rho = W[0];
-        double T = SYS::pressure(W) / rho;
-        double tau = (p.tau_mode == 0) ? p.tau_ref * (p.rho_ref / rho) * sqrt(p.T_ref / T) : p.tau_ref;
-        SYS::source(W, 1.0 / tau, Cs);
-      } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Cs[v] = 0.0;
-      }
+  if (own) {
+    {
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -221,8 +224,8 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         L = L + Cs[v];
         double o;
         if (p.mode == MODE_EULER) o = Ub[v] + (p.cdt * dt) * L;
-        else if (p.mode == MODE_HEUN2) o = 0.5 * p.Ua[v * p.plane + off] + 0.5 * (Ub[v] + dt * L);
-        else o = p.Ua[v * p.plane + off] + dt * L;
+        else if (p.mode == MODE_HEUN2) o = 0.5 * Ua[v] + 0.5 * (Ub[v] + dt * L);
+        else o = Ua[v] + dt * L;
         Un[v] = o;
         if (!implicit_src) p.Uout[v * p.plane + off] = o;
       }
@@ -249,16 +252,17 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       bool fin = true;
 #pragma unroll
       for (int v = 0; v < NV; ++v) fin = fin && isfinite(Un[v]);
-      double Wn[NV];
-      SYS::cons_to_prim(Un, Wn);
-      if (!fin) flag |= ST_NONFINITE;
-      else if (!SYS::admissible(Wn)) flag |= ST_UNREALIZABLE;
-      if (p.do_cfl && flag == 0) {
-        if constexpr (DIM == 1) {
-          rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws);
-        } else {
-          rate = SYS::cell_rate2d(Wn, p.sigma_lim, p.kws, p.dx, p.dy);
-        }
+      if (!fin) {
+        flag |= ST_NONFINITE;
+      } else if (p.do_cfl) {
+        // the last stage of a step: the new state's primitives also give its CFL rate
+        double Wn[NV];
+        SYS::cons_to_prim(Un, Wn);
+        if (!SYS::admissible(Wn)) flag |= ST_UNREALIZABLE;
+        else if constexpr (DIM == 1) rate = SYS::template cell_lambda<0>(Wn, p.sigma_lim, p.kws);
+        else rate = SYS::cell_rate2d(Wn, p.sigma_lim, p.kws, p.dx, p.dy);
+      } else if (!SYS::admissible_cons(Un)) {
+        flag |= ST_UNREALIZABLE;
       }
     }
   }

@@ -43,6 +43,11 @@ MX_HD constexpr int sidx(int i, int j) {
 }
 
 template <class T> MX_HD T sq(T a) { return a * a; }
+// a * b + c: one rounding for the real types (fused multiply-add), the plain expression for
+// the host's counting and dual-number types
+template <class T> MX_HD T tfma(T a, T b, T c) { return a * b + c; }
+template <> MX_HD double tfma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> MX_HD float tfma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <class T> MX_HD T tmax(T a, T b) { return a > b ? a : b; }
 template <class T> MX_HD T tmin(T a, T b) { return a < b ? a : b; }
 template <class T> MX_HD T tabs(T a) { return a < T(0) ? -a : a; }
@@ -227,6 +232,20 @@ struct Sys14 {
   template <class T> MX_HD static T pressure(const T* W) { return (W[4] + W[7] + W[9]) * T(1.0 / 3.0); }
 
   template <class T> MX_HD static bool admissible(const T* W) { return spd_ok(W[0], W + 4); }
+  // the primitives admissible() reads: rho and the pressure tensor
+  MX_HD static constexpr bool admissibility_var(int v) { return v == 0 || (v >= 4 && v < 10); }
+  // admissible(cons_to_prim(U)) without recovering q and R (the same expressions for rho, u, P)
+  template <class T> MX_HD static bool admissible_cons(const T* U) {
+    T rho = U[0];
+    T ir = mrcp(rho);
+    T u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
+    T P[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) P[sidx(i, j)] = U[4 + sidx(i, j)] - rho * (u[i] * u[j]);
+    return spd_ok(rho, P);
+  }
 
   // natural scale of each primitive (rho, c, p, rho c^3, rho c^4) for the neutral-variable
   // test of the common limiter
@@ -546,6 +565,13 @@ struct Sys5 {
 
   template <class T> MX_HD static T pressure(const T* W) { return W[2]; }
   template <class T> MX_HD static bool admissible(const T* W) { return W[0] > T(0) && W[2] > T(0); }
+  MX_HD static constexpr bool admissibility_var(int v) { return v == 0 || v == 2; }
+  template <class T> MX_HD static bool admissible_cons(const T* U) {
+    T rho = U[0];
+    T u = mdiv(U[1], rho);
+    T P = U[2] - rho * u * u;
+    return rho > T(0) && P > T(0);
+  }
 
   template <class T> MX_HD static void scales(const T* W, T* sc) {
     T rho = tabs(W[0]);

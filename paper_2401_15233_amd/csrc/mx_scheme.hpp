@@ -37,15 +37,32 @@ MX_HD T limiter_factor(const T* Wm, const T* Wc, const T* Wp, int kind) {
   return (den == T(1)) ? num : mdiv(num, den);
 }
 
+// The cell's state at its upper (sgn = +1) or lower (sgn = -1) face: Wc +- s/2 with the limited
+// slope s = phi (a + b)/2 and a + b = Wp - Wm, i.e. Wc + sgn (phi/4)(Wp - Wm), one rounding per
+// component.
 template <class SYS, class T>
 MX_HD void face_state(const T* Wm, const T* Wc, const T* Wp, T phi, T sgn, T* Wf) {
+  const T q = sgn * T(0.25) * phi;
 #pragma unroll
-  for (int v = 0; v < SYS::NV; ++v) {
-    T a = Wc[v] - Wm[v];
-    T b = Wp[v] - Wc[v];
-    T s = phi * (a + b) * T(0.5);
-    Wf[v] = Wc[v] + sgn * (s * T(0.5));
+  for (int v = 0; v < SYS::NV; ++v) Wf[v] = tfma(q, Wp[v] - Wm[v], Wc[v]);
+}
+
+// Positivity check of both face states of a cell (rho > 0 and P positive definite): only the
+// components the check reads are reconstructed, with face_state's expressions, so the check
+// decides on exactly the face states the flux evaluation uses.
+template <class SYS, class T>
+MX_HD bool faces_admissible(const T* Wm, const T* Wc, const T* Wp, T phi) {
+  constexpr int NV = SYS::NV;
+  const T q = T(0.25) * phi;
+  T Wu[NV], Wd[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (!SYS::admissibility_var(v)) { Wu[v] = Wd[v] = T(0); continue; }
+    const T d = Wp[v] - Wm[v];
+    Wu[v] = tfma(q, d, Wc[v]);
+    Wd[v] = tfma(-q, d, Wc[v]);
   }
+  return SYS::admissible(Wu) && SYS::admissible(Wd);
 }
 
 template <class SYS, int D, class T>
