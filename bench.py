@@ -621,6 +621,8 @@ def main():
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VECTOR_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VECTOR_PEAK_TFLOPS,
                      'traffic': measured_traffic(),
+                     'traffic_unit': 'HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a '
+                                     'plain copy of known size)',
                      'valu_busy': measured_valu_busy(),
                      'kernel': f'stage_kernel<Sys14,2,2,{0 if head == "fp64" else 1},16,15,256> ({head})',
                      'avg_launch_ms': avg_stage_ms, 'launches': launches,
