@@ -37,15 +37,20 @@ N = 2048
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # algorithmic HBM bytes per cell and stage launch: stage 1 reads U^n and writes U*
-# (2 x 112 B), stage 2 reads U* and U^n and writes U^{n+1} (3 x 112 B)
+# (2 x 112 B), stage 2 reads U* and U^n and writes U^{n+1} (3 x 112 B); the planar kernel
+# (a planar-symmetric state: ten moments carried, the four z-odd ones identically zero)
+# moves 80 B per state
 BYTES_PER_CELL_STAGE = {1: 224.0, 2: 336.0}
+PLANAR_BYTES_PER_CELL_STAGE = {1: 160.0, 2: 240.0}
 # algorithmic FP64 operations per cell and stage launch (each face once per stage, no halo
 # redundancy; add/sub/mul = 1, fma = 2, div/sqrt/exp/log = 1), counted by running the
 # library's own templated device code with a counting scalar:
 # paper_2401_15233_amd/csrc/flopcount.cpp (tests/test_flopcount.py keeps these in sync)
 FLOPS_PER_CELL_STAGE = {1: 4080, 2: 4426}
+PLANAR_FLOPS_PER_CELL_STAGE = {1: 2634, 2: 2895}
 SOURCES_FOR_TRAFFIC = ('paper_2401_15233_amd/csrc/mx_kernels.hip',
                        'paper_2401_15233_amd/csrc/mx_physics.hpp',
+                       'paper_2401_15233_amd/csrc/mx_planar.hpp',
                        'paper_2401_15233_amd/csrc/mx_scheme.hpp',
                        'paper_2401_15233_amd/csrc/mx_bc.hpp',
                        'paper_2401_15233_amd/csrc/mx_internal.hpp')
@@ -458,7 +463,7 @@ def full_run_record(stream, n, steps=2000):
     return {'workload': f'{n}x{n} crossed jets, all {steps} steps from rest',
             'fp64': {'value': n * n * info64['steps'] / (ms64 / 1e3), 'unit': 'cell-updates/s',
                      'ms_per_step': ms64 / max(info64['steps'], 1), 'steps': info64['steps'],
-                     'status': info64['status'], 't': info64['t']},
+                     'status': info64['status'], 't': info64['t'], 'planar_kernel': bool(info64['planar'])},
             'mixed': {'value': n * n * infomx['steps'] / (msmx / 1e3), 'unit': 'cell-updates/s',
                       'ms_per_step': msmx / max(infomx['steps'], 1), 'steps': infomx['steps'],
                       'status': infomx['status'], 'speedup_vs_fp64': ms64 / msmx,
@@ -507,6 +512,8 @@ def main():
     ap.add_argument('--advance', type=int, default=1000,
                     help='untimed steps from rest before the warm-up and the timed steps, so that '
                          'the timed window sits in the middle of the 2000-step workload')
+    ap.add_argument('--no-full-kernel', dest='full_kernel', action='store_false',
+                    help='skip the timed window with the full 14-moment kernel')
     ap.add_argument('--no-full-run', action='store_true',
                     help='skip the full 2000-step FP64 and mixed runs')
     ap.add_argument('--no-sod', action='store_true',
@@ -563,10 +570,11 @@ def main():
     stream = torch.cuda.current_stream()
     W0 = inputs.crossed_jets_initial(n, n)
 
-    def timed(precision, init=None):
+    def timed(precision, init=None, planar=True):
         kw = jets_kwargs(n)
         kw['precision'] = precision
         s = solver.MaxEntSolver(stream=stream, **kw)
+        s.set_planar(planar)
         s.init_state(W0 if init is None else init)
         if a.advance:
             s.step(a.advance, tau_ref=tau)
@@ -591,8 +599,13 @@ def main():
     cells = n * n
     cups = cells * a.steps / (ms / 1e3)
     avg_stage_ms = stage_ms / max(launches, 1)
-    bytes_per_launch = cells * 0.5 * (BYTES_PER_CELL_STAGE[1] + BYTES_PER_CELL_STAGE[2])
-    flops_per_launch = cells * 0.5 * (FLOPS_PER_CELL_STAGE[1] + FLOPS_PER_CELL_STAGE[2])
+    planar = bool(info.get('planar'))
+    bpc = PLANAR_BYTES_PER_CELL_STAGE if planar else BYTES_PER_CELL_STAGE
+    fpc = PLANAR_FLOPS_PER_CELL_STAGE if planar else FLOPS_PER_CELL_STAGE
+    bytes_per_launch = cells * 0.5 * (bpc[1] + bpc[2])
+    flops_per_launch = cells * 0.5 * (fpc[1] + fpc[2])
+    bytes_per_update = bpc[1] + bpc[2]
+    sysname = 'Sys14P' if planar else 'Sys14'
     achieved = flops_per_launch / (avg_stage_ms / 1e3) / 1e12
     hbm_achieved = bytes_per_launch / (avg_stage_ms / 1e3) / 1e9
     out = {
@@ -615,8 +628,11 @@ def main():
                    'precision': 'fp64',
                    'steps_in_workload': 2000, 'precision_mode': head,
                    'timed_window': f'steps {a.advance + a.warmup + 1}..{a.advance + a.warmup + a.steps} '
-                                   f'of the run from rest'},
-        'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms / 1e3) / 1e9,
+                                   f'of the run from rest',
+                   'stage_kernel': ('planar: the state is even in v_z, so u_z = P_xz = P_yz = q_z = 0 '
+                                    'and the kernel carries the ten other moments' if planar
+                                    else 'full 14-moment')},
+        'hbm_gbs_algorithmic': cells * bytes_per_update * a.steps / (ms / 1e3) / 1e9,
         'sim_time_reached': info['t'],
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VECTOR_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -624,7 +640,7 @@ def main():
                      'traffic_unit': 'HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a '
                                      'plain copy of known size)',
                      'valu_busy': measured_valu_busy(),
-                     'kernel': f'stage_kernel<Sys14,2,2,{0 if head == "fp64" else 1},16,15,256> ({head})',
+                     'kernel': f'stage_kernel<{sysname},2,2,{0 if head == "fp64" else 1},16,15,256> ({head})',
                      'avg_launch_ms': avg_stage_ms, 'launches': launches,
                      'flops_per_launch': flops_per_launch,
                      'hbm_algorithmic_bytes_per_launch': bytes_per_launch,
@@ -649,7 +665,7 @@ def main():
             'ms_per_step': ms_m / a.steps, 'speedup_vs_fp64': ms / ms_m,
             'avg_stage_launch_ms': avg_m,
             'alu_tflops_algorithmic': flops_per_launch / (avg_m / 1e3) / 1e12,
-            'hbm_gbs_algorithmic': cells * 560.0 * a.steps / (ms_m / 1e3) / 1e9,
+            'hbm_gbs_algorithmic': cells * bytes_per_update * a.steps / (ms_m / 1e3) / 1e9,
             'l1_rel_deviation_from_fp64_per_moment': [float(x) for x in (d / ref).cpu()],
             # the FP64 run's own L1 change when its initial state carries one random FP32
             # rounding (+-2^-24 relative): how far this flow amplifies single-precision
@@ -657,6 +673,21 @@ def main():
             'fp64_l1_change_under_fp32_input_rounding_per_moment': fp64_sensitivity(),
             'fp64_reevaluated_face_state_fraction':
                 info_m['n_fp64_states'] / max(info_m['n_face_states'], 1),
+        }
+    if planar and a.full_kernel:
+        # the same window with the full 14-moment kernel (planar mode off)
+        ms_f, stage_ms_f, launches_f, _, U_f = timed(head, planar=False)
+        d = (U_f - U_head).abs().reshape(14, -1).sum(1)
+        ref = U_head.abs().reshape(14, -1).sum(1).clamp_min(1e-300)
+        avg_f = stage_ms_f / max(launches_f, 1)
+        out['full_kernel'] = {
+            'value': cells * a.steps / (ms_f / 1e3), 'unit': 'cell-updates/s',
+            'ms_per_step': ms_f / a.steps, 'avg_stage_launch_ms': avg_f,
+            'planar_speedup': ms_f / ms,
+            'alu_tflops_algorithmic': cells * 0.5 * (FLOPS_PER_CELL_STAGE[1] + FLOPS_PER_CELL_STAGE[2])
+                                      / (avg_f / 1e3) / 1e12,
+            # rounding-order differences, amplified over the run like any rounding change
+            'l1_rel_deviation_from_planar_per_moment': [float(x) for x in (d / ref).cpu()],
         }
     if not a.no_full_run:
         out['full_run'] = full_run_record(stream, n)

@@ -1,6 +1,7 @@
 // Algorithmic operation count of one cell-update of the 2D 14-moment step (MUSCL + common
 // limiter + closure + wave speeds + HLL + BGK + SSP-RK2 + CFL), obtained by running the
-// library's own templated device code on the host with a counting scalar type.
+// library's own templated device code on the host with a counting scalar type: the full
+// 14-moment kernel and the planar one (ten moments of a planar-symmetric state).
 //
 // "Algorithmic" means the work the method needs per cell: every face is counted once per
 // stage (each cell owns one x-face and one y-face), the cell is converted to primitives once
@@ -42,6 +43,7 @@ CD mexp(CD a);
 CD mlog(CD a);
 
 #include "mx_scheme.hpp"
+#include "mx_planar.hpp"
 #include <cmath>
 
 CD msqrt(CD a) { g_ops.sqrt++; return CD(std::sqrt(a.v)); }
@@ -49,14 +51,19 @@ CD mexp(CD a) { g_ops.exp++; return CD(std::exp(a.v)); }
 CD mlog(CD a) { g_ops.log++; return CD(std::log(a.v)); }
 
 using mx::Sys14;
+using mx::Sys14P;
 
 // A bimodal beam-crossing state (anisotropic P, non-zero q, super-Maxwellian R) and two
 // slightly different neighbours on each side, so that every branch a typical subsonic face
 // of the crossed-jets flow takes is exercised (HLL middle state, limiter with phi in (0,1)).
+// (planar-symmetric: u_z = P_xz = P_yz = q_z = 0; SYS::from14 keeps the moments SYS carries)
+template <class SYS>
 static void state(double f, CD* W) {
   const double base[14] = {0.35, 1.2, 0.1, 0.0, 1.6, 0.4, 0.0, 0.9, 0.0, 0.45,
                            0.6, -0.2, 0.0, 9.0};
-  for (int v = 0; v < 14; ++v) W[v] = CD(base[v] * (1.0 + 0.01 * f * (1 + (v % 3))));
+  CD W14[14];
+  for (int v = 0; v < 14; ++v) W14[v] = CD(base[v] * (1.0 + 0.01 * f * (1 + (v % 3))));
+  SYS::from14(W14, W);
 }
 
 static Ops delta(const Ops& a, const Ops& b) {
@@ -67,32 +74,34 @@ static Ops delta(const Ops& a, const Ops& b) {
 }
 
 // one stage of one cell; `last` adds the CFL reduction input of the new state
+template <class SYS>
 static void cell_stage(bool last) {
-  CD W[5][14], U[14], Wc[14];
-  for (int k = 0; k < 5; ++k) state(k - 2.0, W[k]);
-  Sys14::prim_to_cons(W[2], U);
+  constexpr int NV = SYS::NV;
+  CD W[5][NV], U[NV], Wc[NV];
+  for (int k = 0; k < 5; ++k) state<SYS>(k - 2.0, W[k]);
+  SYS::prim_to_cons(W[2], U);
   // primitive recovery of the stage input (once per cell: the update takes the centre's
   // primitives from the loaded tile)
-  Sys14::cons_to_prim(U, Wc);
+  SYS::cons_to_prim(U, Wc);
   CD sl(1e-4), kws(1.0);
   for (int d = 0; d < 2; ++d) {
     // common limiter factor and the positivity check of the cell's two face states
-    CD phi = mx::limiter_factor<Sys14>(W[1], W[2], W[3], 0);
-    (void)mx::faces_admissible<Sys14>(W[1], W[2], W[3], phi);
+    CD phi = mx::limiter_factor<SYS>(W[1], W[2], W[3], 0);
+    (void)mx::faces_admissible<SYS>(W[1], W[2], W[3], phi);
     // the cell's own face along d: left state from this cell, right state from the next
-    CD WL[14], WR[14], Fh[14];
-    mx::face_state<Sys14>(W[1], W[2], W[3], phi, CD(1.0), WL);
-    mx::face_state<Sys14>(W[2], W[3], W[4], phi, CD(-1.0), WR);
-    if (d == 0) mx::face_flux<Sys14, 0>(WL, WR, sl, kws, 0, Fh);
-    else mx::face_flux<Sys14, 1>(WL, WR, sl, kws, 0, Fh);
+    CD WL[NV], WR[NV], Fh[NV];
+    mx::face_state<SYS>(W[1], W[2], W[3], phi, CD(1.0), WL);
+    mx::face_state<SYS>(W[2], W[3], W[4], phi, CD(-1.0), WR);
+    if (d == 0) mx::face_flux<SYS, 0>(WL, WR, sl, kws, 0, Fh);
+    else mx::face_flux<SYS, 1>(WL, WR, sl, kws, 0, Fh);
   }
   // update: flux differences, BGK source with local tau, Heun combination, admissibility
-  CD C[14], Un[14], Wn[14];
+  CD C[NV], Un[NV], Wn[NV];
   CD rho = Wc[0];
-  CD T = Sys14::pressure(Wc) / rho;
+  CD T = SYS::pressure(Wc) / rho;
   CD tau = CD(0.006) * (CD(1.0) / rho) * msqrt(CD(1.0) / T);
-  Sys14::source(Wc, CD(1.0) / tau, C);
-  for (int v = 0; v < 14; ++v) {
+  SYS::source(Wc, CD(1.0) / tau, C);
+  for (int v = 0; v < NV; ++v) {
     CD L = -(U[v] - Wc[v]) * CD(2048.0);
     L = L - (U[v] - W[1][v]) * CD(2048.0);
     L = L + C[v];
@@ -100,34 +109,44 @@ static void cell_stage(bool last) {
   }
   if (last) {
     // the last stage: the new state's primitives give the check and the next CFL rate
-    Sys14::cons_to_prim(Un, Wn);
-    (void)Sys14::admissible(Wn);
-    CD r = Sys14::cell_rate2d(Wn, sl, kws, CD(1.0 / 2048), CD(1.0 / 2048));
+    SYS::cons_to_prim(Un, Wn);
+    (void)SYS::admissible(Wn);
+    CD r = SYS::cell_rate2d(Wn, sl, kws, CD(1.0 / 2048), CD(1.0 / 2048));
     (void)r;
   } else {
-    (void)Sys14::admissible_cons(Un);
+    (void)SYS::admissible_cons(Un);
   }
 }
 
-int main() {
+template <class SYS>
+static void count(Ops& s1, Ops& s2, Ops& f) {
   Ops a = g_ops;
-  cell_stage(false);
-  Ops s1 = delta(a, g_ops);
+  cell_stage<SYS>(false);
+  s1 = delta(a, g_ops);
   a = g_ops;
-  cell_stage(true);
-  Ops s2 = delta(a, g_ops);
+  cell_stage<SYS>(true);
+  s2 = delta(a, g_ops);
   // one face evaluation alone, for reference
-  CD WL[14], WR[14], Fh[14];
-  state(0.0, WL);
-  state(1.0, WR);
+  CD WL[SYS::NV], WR[SYS::NV], Fh[SYS::NV];
+  state<SYS>(0.0, WL);
+  state<SYS>(1.0, WR);
   a = g_ops;
-  mx::face_flux<Sys14, 0>(WL, WR, CD(1e-4), CD(1.0), 0, Fh);
-  Ops f = delta(a, g_ops);
-  long long total = s1.flops() + s2.flops();
+  mx::face_flux<SYS, 0>(WL, WR, CD(1e-4), CD(1.0), 0, Fh);
+  f = delta(a, g_ops);
+}
+
+int main() {
+  Ops s1, s2, f, p1, p2, pf;
+  count<Sys14>(s1, s2, f);
+  count<Sys14P>(p1, p2, pf);
   printf("{\"system\": 14, \"dim\": 2, \"scheme\": \"MUSCL-minmod common limiter + HLL + SSP-RK2 + BGK + CFL\", "
          "\"flops_per_cell_update\": %lld, \"flops_stage1\": %lld, \"flops_stage2\": %lld, "
-         "\"div\": %lld, \"sqrt\": %lld, \"exp\": %lld, \"log\": %lld, \"flops_per_face\": %lld}\n",
-         total, s1.flops(), s2.flops(), s1.div + s2.div, s1.sqrt + s2.sqrt, s1.exp + s2.exp,
-         s1.log + s2.log, f.flops());
+         "\"div\": %lld, \"sqrt\": %lld, \"exp\": %lld, \"log\": %lld, \"flops_per_face\": %lld, "
+         "\"planar_flops_per_cell_update\": %lld, \"planar_flops_stage1\": %lld, "
+         "\"planar_flops_stage2\": %lld, \"planar_div\": %lld, \"planar_sqrt\": %lld, "
+         "\"planar_flops_per_face\": %lld}\n",
+         s1.flops() + s2.flops(), s1.flops(), s2.flops(), s1.div + s2.div, s1.sqrt + s2.sqrt,
+         s1.exp + s2.exp, s1.log + s2.log, f.flops(), p1.flops() + p2.flops(), p1.flops(),
+         p2.flops(), p1.div + p2.div, p1.sqrt + p2.sqrt, pf.flops());
   return 0;
 }

@@ -26,12 +26,15 @@ __device__ __forceinline__ int map_axis(int g, int n, int lo, int hi, int& refl)
 
 // the jet on `wall` (0 x-low, 1 x-high, 2 y-low, 3 y-high) whose band holds boundary cell s
 // (a row for the x walls, a column for the y walls; the last jet listed if bands overlap),
-// or -1
+// or -1 (the loop runs over the four parameter slots, so every index into the kernel's
+// parameter block is static)
 __device__ __forceinline__ int jet_on_wall(const StageParams& p, int wall, int s) {
   const double c = (wall < 2) ? p.y0 + ((double)s + 0.5) * p.dy : p.x0 + ((double)s + 0.5) * p.dx;
   int hit = -1;
-  for (int k = 0; k < p.n_jets; ++k)
-    if (p.jet_wall[k] == wall && c >= p.jet_yc[k] - 0.5 * p.jet_w[k] && c <= p.jet_yc[k] + 0.5 * p.jet_w[k])
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < p.n_jets && p.jet_wall[k] == wall && c >= p.jet_yc[k] - 0.5 * p.jet_w[k] &&
+        c <= p.jet_yc[k] + 0.5 * p.jet_w[k])
       hit = k;
   return hit;
 }
@@ -50,39 +53,66 @@ __device__ __forceinline__ void jet_state(const StageParams& p, int k, double* W
   W[13] = 15.0 * pj * pj / p.jet_rho;
 }
 
+// where the stencil reads ghost or interior cell (gi, gj): the source cell and whether the
+// state is mirrored across an x or a y wall
+struct HaloSrc {
+  int si, sj, rx, ry;
+};
+
+// first half of load_prims: the conserved state of the source cell (the loads only, so that a
+// thread can issue the loads of several cells before it converts any)
 template <class SYS>
-__device__ __forceinline__ void load_prims(const StageParams& p, const double* U, int gi, int gj,
-                                           double* W) {
-  constexpr int NV = SYS::NV;
-  int rx = 0, ry = 0;
-  int si = map_axis(gi, p.nx, p.bc[0], p.bc[1], rx);
-  int sj = map_axis(gj, p.ny, p.bc[2], p.bc[3], ry);
-  double Uc[NV];
-  const double* src = U + (long long)sj * p.pitch + si;
+__device__ __forceinline__ HaloSrc load_cons(const StageParams& p, const double* U, int gi, int gj,
+                                             double* Uc) {
+  HaloSrc h;
+  h.rx = 0; h.ry = 0;
+  h.si = map_axis(gi, p.nx, p.bc[0], p.bc[1], h.rx);
+  h.sj = map_axis(gj, p.ny, p.bc[2], p.bc[3], h.ry);
+  const double* src = U + (long long)h.sj * p.pitch + h.si;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Uc[v] = src[v * p.plane];
+  for (int v = 0; v < SYS::NV; ++v) Uc[v] = src[SYS::plane_of(v) * p.plane];
+  return h;
+}
+
+// second half: primitives, mirrored components, jet inflow states in the jets' ghost cells
+template <class SYS>
+__device__ __forceinline__ void finish_prims(const StageParams& p, const HaloSrc& h, int gi, int gj,
+                                             const double* Uc, double* W) {
+  constexpr int NV = SYS::NV;
   SYS::cons_to_prim(Uc, W);
-  if (rx) {
+  if (h.rx) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       if (SYS::odd(v, 0)) W[v] = -W[v];
   }
-  if (ry) {
+  if (h.ry) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       if (SYS::odd(v, 1)) W[v] = -W[v];
   }
-  if constexpr (NV == 14) {
+  if constexpr (SYS::JETS) {
     // ghost cells only (one unsigned compare per axis catches both sides)
     if (p.n_jets > 0 && ((unsigned)gi >= (unsigned)p.nx || (unsigned)gj >= (unsigned)p.ny)) {
       const int wall = gi < 0 ? 0 : (gi >= p.nx ? 1 : (gj < 0 ? 2 : 3));
       const int kind = wall == 0 ? p.bc[0] : (wall == 1 ? p.bc[1] : (wall == 2 ? p.bc[2] : p.bc[3]));
       if (kind == 3) {
-        const int k = jet_on_wall(p, wall, wall < 2 ? sj : si);
-        if (k >= 0) jet_state(p, k, W);
+        const int k = jet_on_wall(p, wall, wall < 2 ? h.sj : h.si);
+        if (k >= 0) {
+          double Wj[14];
+          jet_state(p, k, Wj);
+          SYS::from14(Wj, W);
+        }
       }
     }
   }
+}
+
+template <class SYS>
+__device__ __forceinline__ void load_prims(const StageParams& p, const double* U, int gi, int gj,
+                                           double* W) {
+  double Uc[SYS::NV];
+  const HaloSrc h = load_cons<SYS>(p, U, gi, gj, Uc);
+  finish_prims<SYS>(p, h, gi, gj, Uc, W);
 }
 
 }  // namespace mx

@@ -19,6 +19,7 @@
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
 #include "mx_bc.hpp"
+#include "mx_planar.hpp"
 
 namespace mx {
 
@@ -79,7 +80,10 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       if (gi < p.nx && gj < p.ny) {
         long long off = (long long)gj * p.pitch + gi;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) p.Uout[v * p.plane + off] = p.Ub[v * p.plane + off];
+        for (int v = 0; v < NV; ++v) {
+          const long long o = SYS::plane_of(v) * p.plane + off;
+          p.Uout[o] = p.Ub[o];
+        }
       }
     }
     return;
@@ -89,12 +93,30 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   int nstates = 0;  // face states evaluated
 
   // 1. tile + halo -> primitives in LDS
-  for (int c = t; c < NL; c += NT) {
-    int li = c % LX, lj = c / LX;
-    double W[NV];
-    load_prims<SYS>(p, p.Ub, i0 + li - G, (DIM == 2) ? j0 + lj - G : 0, W);
+  // (a thread issues the loads of all its cells before it converts any)
+  {
+    constexpr int NR = (NL + NT - 1) / NT;
+    double Uh[NR][NV];
+    HaloSrc hs[NR];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sW[v * NL + c] = W[v];
+    for (int r = 0; r < NR; ++r) {
+      const int c = t + r * NT;
+      if (c < NL) {
+        const int li = c % LX, lj = c / LX;
+        hs[r] = load_cons<SYS>(p, p.Ub, i0 + li - G, (DIM == 2) ? j0 + lj - G : 0, Uh[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int c = t + r * NT;
+      if (c < NL) {
+        const int li = c % LX, lj = c / LX;
+        double W[NV];
+        finish_prims<SYS>(p, hs[r], i0 + li - G, (DIM == 2) ? j0 + lj - G : 0, Uh[r], W);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sW[v * NL + c] = W[v];
+      }
+    }
   }
   __syncthreads();
 
@@ -165,7 +187,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       } else {
         lds(fi, fj - 1, WL); lds(fi, fj, WR);
       }
-      if constexpr (SYS::NV == 14) {
+      {
         if constexpr (PREC == 0) face_flux<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
         else if constexpr (PREC == 1) face_flux_mixed<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy, n64);
         else face_flux_fp32<SYS, 1>(WL, WR, p.sigma_lim, p.kws, p.flux, Fy);
@@ -184,10 +206,10 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   double Ub[NV], Ua[NV], Cs[NV];
   if (own) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + off];
+    for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[SYS::plane_of(v) * p.plane + off];
     if (p.mode != MODE_EULER) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Ua[v] = p.Ua[v * p.plane + off];
+      for (int v = 0; v < NV; ++v) Ua[v] = p.Ua[SYS::plane_of(v) * p.plane + off];
     }
     if (p.use_source && !implicit_src) {
       double W[NV];
@@ -227,7 +249,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
         else if (p.mode == MODE_HEUN2) o = 0.5 * Ua[v] + 0.5 * (Ub[v] + dt * L);
         else o = Ua[v] + dt * L;
         Un[v] = o;
-        if (!implicit_src) p.Uout[v * p.plane + off] = o;
+        if (!implicit_src) p.Uout[SYS::plane_of(v) * p.plane + off] = o;
       }
       if (implicit_src) {
         // backward-Euler BGK relaxation of the transported state (forward-Euler stages only):
@@ -246,7 +268,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           Un[v] = (Un[v] + h * Ue[v]) * w;
-          p.Uout[v * p.plane + off] = Un[v];
+          p.Uout[SYS::plane_of(v) * p.plane + off] = Un[v];
         }
       }
       bool fin = true;
@@ -367,7 +389,18 @@ __global__ void ctrl_reset_kernel(DevCtrl* c, double t0) {
   if (threadIdx.x == 0) {
     c->dt = 0.0; c->t = t0; c->t_end = 0.0; c->dt_fixed = 0.0; c->dt_last = 0.0;
     c->maxrate = 0ull; c->step = 0; c->n_fallback = 0; c->status = 0; c->fail_step = 0x7fffffff;
-    c->n_fp64 = 0; c->n_states = 0; c->n_sigma_limited = 0;
+    c->n_fp64 = 0; c->n_states = 0; c->n_sigma_limited = 0; c->nonplanar = 0;
+  }
+}
+
+// zero the z-odd planes (u_z, P_xz, P_yz, q_z) of a 14-moment field
+__global__ __launch_bounds__(256) void zero_planes_kernel(double* U, long long plane) {
+  const long long n = 4 * plane;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+    const int w = (int)(k / plane);
+    const long long o = k - w * plane;
+    const int v = w == 0 ? 3 : (w == 1 ? 6 : (w == 2 ? 8 : 12));
+    U[v * plane + o] = 0.0;
   }
 }
 
@@ -378,7 +411,7 @@ __global__ void ingest_kernel(int repr, const double* src, double* U, int nx, in
   constexpr int NV = SYS::NV;
   long long n = (long long)nx * ny;
   long long plane = (long long)ny * pitch;
-  int bad = 0;
+  int bad = 0, np = 0;
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (long long)gridDim.x * blockDim.x) {
     int i = (int)(k % nx), j = (int)(k / nx);
@@ -402,9 +435,16 @@ __global__ void ingest_kernel(int repr, const double* src, double* U, int nx, in
     }
     if (!fin) bad |= ST_NONFINITE;
     else if (!SYS::admissible(W)) bad |= ST_UNREALIZABLE;
+    // planar symmetry (14 moments): u_z, P_xz, P_yz and q_z all exactly zero
+    if constexpr (NV == 14)
+      if (Uc[3] != 0.0 || Uc[6] != 0.0 || Uc[8] != 0.0 || Uc[12] != 0.0) np = 1;
   }
   bad = wave_or(bad);
   if ((threadIdx.x & 63) == 0 && bad) atomicOr(&c->status, bad);
+  if constexpr (NV == 14) {
+    np = wave_or(np);
+    if ((threadIdx.x & 63) == 0 && np) atomicOr(&c->nonplanar, 1);
+  }
 }
 
 // Closing moments of a cell state (dimensional, at sigma_bar = max(sigma, sigma_lim)):
@@ -502,21 +542,24 @@ static hipError_t launch_stage_t(const StageParams& p, hipStream_t s) {
 }
 
 template <int PREC>
-static hipError_t launch_stage_p(int system, int dim, int order, const StageParams& p, hipStream_t s) {
+static hipError_t launch_stage_p(int system, int dim, int order, bool planar, const StageParams& p,
+                                 hipStream_t s) {
   if (system == 5) {
     if (dim != 1) return hipErrorInvalidValue;
     return order == 2 ? launch_stage_t<Sys5, 1, 2, PREC>(p, s) : launch_stage_t<Sys5, 1, 1, PREC>(p, s);
   }
   if (dim == 1)
     return order == 2 ? launch_stage_t<Sys14, 1, 2, PREC>(p, s) : launch_stage_t<Sys14, 1, 1, PREC>(p, s);
+  if (planar)
+    return order == 2 ? launch_stage_t<Sys14P, 2, 2, PREC>(p, s) : launch_stage_t<Sys14P, 2, 1, PREC>(p, s);
   return order == 2 ? launch_stage_t<Sys14, 2, 2, PREC>(p, s) : launch_stage_t<Sys14, 2, 1, PREC>(p, s);
 }
 
-hipError_t launch_stage(int system, int dim, int order, int precision, const StageParams& p,
-                        hipStream_t s) {
-  if (precision == 1) return launch_stage_p<1>(system, dim, order, p, s);
-  if (precision == 2) return launch_stage_p<2>(system, dim, order, p, s);
-  return launch_stage_p<0>(system, dim, order, p, s);
+hipError_t launch_stage(int system, int dim, int order, int precision, bool planar,
+                        const StageParams& p, hipStream_t s) {
+  if (precision == 1) return launch_stage_p<1>(system, dim, order, planar, p, s);
+  if (precision == 2) return launch_stage_p<2>(system, dim, order, planar, p, s);
+  return launch_stage_p<0>(system, dim, order, planar, p, s);
 }
 
 hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s) {
@@ -541,6 +584,15 @@ hipError_t launch_ctrl_set(DevCtrl* c, double dt_fixed, double t_end, hipStream_
 
 hipError_t launch_ctrl_reset(DevCtrl* c, double t0, hipStream_t s) {
   hipLaunchKernelGGL(ctrl_reset_kernel, dim3(1), dim3(64), 0, s, c, t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_planes(double* U, long long plane, int nv, hipStream_t s) {
+  if (nv != 14) return hipSuccess;
+  long long n = 4 * plane;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(zero_planes_kernel, dim3(grid), dim3(256), 0, s, U, plane);
   return hipGetLastError();
 }
 

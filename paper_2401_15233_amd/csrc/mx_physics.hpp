@@ -179,7 +179,12 @@ template <class T> MX_HD BYEC<T> byec(T sw, T Pdd) {
 // ===================================================================== 14 moments
 struct Sys14 {
   static constexpr int NV = 14;
-  enum { RHO = 0, UX = 1, PXX = 4, QX = 10, RR = 13 };
+  static constexpr bool JETS = true;       // jet inflow boundaries apply
+  MX_HD static constexpr int plane_of(int v) { return v; }   // storage plane of moment v
+  template <class T> MX_HD static void from14(const T* W14, T* W) {
+#pragma unroll
+    for (int v = 0; v < 14; ++v) W[v] = W14[v];
+  }
 
   template <class T> MX_HD static void cons_to_prim(const T* U, T* W) {
     T rho = U[0];
@@ -544,6 +549,8 @@ struct Sys14 {
 // ===================================================================== 5 moments
 struct Sys5 {
   static constexpr int NV = 5;
+  static constexpr bool JETS = false;
+  MX_HD static constexpr int plane_of(int v) { return v; }
 
   template <class T> MX_HD static void cons_to_prim(const T* U, T* W) {
     T rho = U[0];

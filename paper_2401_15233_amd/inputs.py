@@ -166,6 +166,45 @@ def random_states14(n, seed=0):
     return W
 
 
+def random_planar_states14(n, seed=0):
+    """n realizable 14-moment states whose distribution is even in the z velocity (u_z =
+    P_xz = P_yz = q_z = 0 exactly): in-plane Maxwellians, 2- and 3-beam mixtures with
+    in-plane mean velocities, particle sets mirrored in v_z, with random density scale,
+    velocity scale and in-plane boost."""
+    rng = np.random.default_rng(seed)
+    fam = rng.integers(0, 4, size=n)
+    W = np.empty((14, n))
+    i0 = np.nonzero(fam == 0)[0]
+    W[:, i0] = _maxw14(np.ones(len(i0)), 0.0, 0.0, 0.0, np.ones(len(i0)))
+    for f, K in ((1, 2), (2, 3)):
+        ii = np.nonzero(fam == f)[0]
+        if len(ii):
+            w = rng.uniform(0.05, 1.0, size=(K, len(ii)))
+            m = rng.normal(0.0, 1.5, size=(K, 3, len(ii)))
+            m[:, 2] = 0.0
+            T = rng.uniform(0.05, 1.5, size=(K, len(ii)))
+            W[:, ii] = beam_mixture14(w, m, T)
+    ii = np.nonzero(fam == 3)[0]
+    if len(ii):
+        M = 4
+        w = rng.uniform(0.1, 1.0, size=(M, len(ii)))
+        v = rng.normal(0.0, 1.0, size=(M, 3, len(ii)))
+        vm = v.copy()
+        vm[:, 2] = -vm[:, 2]
+        W[:, ii] = particle_moments14(np.concatenate([w, w]), np.concatenate([v, vm]))
+    # the z-odd moments vanish by symmetry; drop the sums' rounding residue
+    W[[3, 6, 8, 12]] = 0.0
+    a = np.exp(rng.uniform(math.log(1e-3), math.log(10.0), size=n))
+    b = np.exp(rng.uniform(math.log(0.3), math.log(3.0), size=n))
+    boost = rng.normal(0.0, 2.0, size=(2, n))
+    W[0] *= a
+    W[1:3] = W[1:3] * b + boost
+    W[4:10] *= a * b**2
+    W[10:13] *= a * b**3
+    W[13] *= a * b**4
+    return W
+
+
 def random_states5(n, seed=0):
     rng = np.random.default_rng(seed)
     fam = rng.integers(0, 4, size=n)
@@ -253,8 +292,10 @@ def crossed_jets_developed(nx, ny, seed=0, reach=0.6, smear=0.02):
     return beam_mixture14(np.stack(wts), np.stack(means), np.stack(temps))
 
 
-def random_smooth_field14(nx, ny, seed=0):
-    """Smooth random realizable 2D field (beam mixtures whose parameters vary smoothly)."""
+def random_smooth_field14(nx, ny, seed=0, planar=False):
+    """Smooth random realizable 2D field (beam mixtures whose parameters vary smoothly).
+    planar=True: the beams move in the x-y plane, so the field is even in v_z (u_z = P_xz =
+    P_yz = q_z = 0 exactly); the other parameters are drawn as for planar=False."""
     rng = np.random.default_rng(seed)
     x = cell_centres(nx)[None, :]
     y = cell_centres(ny)[:, None]
@@ -270,6 +311,8 @@ def random_smooth_field14(nx, ny, seed=0):
     w = np.stack([np.exp(smooth(0.3, 0.0)) for _ in range(K)])
     m = np.stack([np.stack([smooth(0.5, rng.normal()) for _ in range(3)]) for _ in range(K)])
     T = np.stack([np.exp(smooth(0.2, 0.0)) for _ in range(K)])
+    if planar:
+        m[:, 2] = 0.0
     return beam_mixture14(w, m, T)
 
 

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.maxent_abi_version() == 3
+    assert lib.maxent_abi_version() == 4
 
 
 def test_struct_layouts_match_header():
@@ -44,8 +44,38 @@ def test_struct_layouts_match_header():
     assert S.Problem.jet_wall.offset == 216
     assert ctypes.sizeof(S.Numerics) == 5 * 4 + 4 + 3 * 8 + 4 + 4
     assert S.Numerics.source_implicit.offset == 52
-    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4
     assert S.Info.n_sigma_limited.offset == 56 and S.Info.fp64_fraction.offset == 64
+    assert S.Info.planar.offset == 72
+
+
+def test_struct_layout_matches_the_c_compiler(tmp_path):
+    """sizeof / offsetof of the header's structs, printed by a C program built with the host
+    compiler, equal the ctypes mirrors'."""
+    import shutil
+    import subprocess
+    cc = shutil.which('gcc') or shutil.which('cc')
+    if cc is None:
+        pytest.skip('no host C compiler')
+    structs = {'maxent_problem': S.Problem, 'maxent_numerics': S.Numerics, 'maxent_info': S.Info,
+               'maxent_instance': S.Instance, 'maxent_batch_info': S.BatchInfo,
+               'maxent_instance_info': S.InstanceInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / 'layout.c'
+    src.write_text('\n'.join(lines) + '\n')
+    exe = tmp_path / 'layout'
+    subprocess.run([cc, '-std=c99', str(src), '-o', str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split('\n')
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, 'size')] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 @pytest.mark.parametrize('bad', [

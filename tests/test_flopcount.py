@@ -22,3 +22,7 @@ def test_bench_flop_constants_match_the_counter(tmp_path):
     out = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
     import bench
     assert bench.FLOPS_PER_CELL_STAGE == {1: out['flops_stage1'], 2: out['flops_stage2']}
+    assert bench.PLANAR_FLOPS_PER_CELL_STAGE == {1: out['planar_flops_stage1'],
+                                                 2: out['planar_flops_stage2']}
+    # the planar kernel carries 10 of the 14 moments (the z-odd four vanish by symmetry)
+    assert bench.PLANAR_BYTES_PER_CELL_STAGE == {k: v * 10 / 14 for k, v in bench.BYTES_PER_CELL_STAGE.items()}

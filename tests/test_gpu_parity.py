@@ -35,8 +35,9 @@ TAU_SOD = I.kn_to_tau_ref(0.01)
 TAU_JET = I.kn_to_tau_ref(0.1, L_ref=0.1)
 
 
-def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True):
+def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, planar=True):
     s = S.MaxEntSolver(**kw)
+    s.set_planar(planar)
     s.init_state(np.ascontiguousarray(W0))
     info = s.step(n, dt=dt, tau_ref=tau_ref, t_end=t_end, check=check)
     U = s.get('conserved').cpu().numpy()
@@ -44,9 +45,9 @@ def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True):
     return U, info
 
 
-def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, trials=3):
+def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, trials=3, planar=True):
     """Run both sides, print the errors, assert the condition-aware bar."""
-    Ug, info = gpu_run(S, kw, W0, n if n is not None else 20000, dt, tau_ref, t_end, check)
+    Ug, info = gpu_run(S, kw, W0, n if n is not None else 20000, dt, tau_ref, t_end, check, planar)
     base, spread, t, nst, (s_in, s_mid) = ob.oracle_with_spread(
         kw, W0, nsteps=n, dt=dt, tau_ref=tau_ref, t_end=t_end, trials=trials, check=check,
         parts=True)
@@ -58,7 +59,7 @@ def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, tria
 
     print(f'{name}: field-relative error max {err.max():.2e}, oracle spread max: input '
           f'{rel(s_in):.2e}, intermediate {rel(s_mid):.2e}; bound use {ratio:.2f}; '
-          f'steps gpu {info["steps"]} oracle {nst}', flush=True)
+          f'steps gpu {info["steps"]} oracle {nst}; planar kernel {info["planar"]}', flush=True)
     print(f'   per moment {np.array2string(err, precision=1)}', flush=True)
     assert ok, (f'{name}: error exceeds 1e-12 + {ob.SPREAD_FACTOR:g} x oracle spread '
                 f'(ratio {ratio:.2f})')
@@ -158,14 +159,21 @@ def test_random_states_one_step_collisionless(gpu_lib):
 
 
 # ------------------------------------------------------------------ 2D
-def test_jets_2d_developed_field(gpu_lib):
+@pytest.mark.parametrize('planar', [True, False])
+def test_jets_2d_developed_field(gpu_lib, planar):
+    """The developed crossed-jets field is planar-symmetric: the planar kernel (ten moments)
+    runs by default, the full 14-moment kernel when planar mode is off; both against the
+    oracle."""
     nx, ny = 70, 50   # ragged: 4 tiles of 16 + 6, 3 tiles of 15 + 5
     kw = dict(JETS, nx=nx, ny=ny)
     W0 = I.crossed_jets_developed(nx, ny, seed=2)
     for n_steps in (1, 4):
         Ug, info, base, t, n = compare(f'jets 70x50 {n_steps} steps', gpu_lib, kw, W0, n_steps,
-                                       tau_ref=TAU_JET)
+                                       tau_ref=TAU_JET, planar=planar)
         assert abs(info['t'] - t) < 1e-12 * t
+        assert info['planar'] == int(planar)
+        if planar:
+            assert np.all(Ug[[3, 6, 8, 12]] == 0.0)
 
 
 def test_jets_2d_inflated_wave_speeds(gpu_lib):
@@ -190,12 +198,17 @@ def test_jets_2d_from_rest_second_order(gpu_lib):
             tau_ref=TAU_JET)
 
 
-def test_2d_periodic_reflective_smooth(gpu_lib):
+@pytest.mark.parametrize('planar', [False, True])
+def test_2d_periodic_reflective_smooth(gpu_lib, planar):
+    """A smooth 3D field (full kernel) and a planar-symmetric one (planar kernel), periodic in
+    x, reflective in y, midpoint, van Albada, Rusanov."""
     nx, ny = 40, 33
     kw = dict(JETS, nx=nx, ny=ny, bc=('periodic', 'periodic', 'reflective', 'reflective'),
               jets=[], integrator='midpoint', limiter='vanalbada', flux='rusanov')
-    compare('2d periodic/reflective', gpu_lib, kw, I.random_smooth_field14(nx, ny, seed=8), 3,
-            tau_ref=0.03)
+    Ug, info, _, _, _ = compare(f'2d periodic/reflective planar={planar}', gpu_lib, kw,
+                                I.random_smooth_field14(nx, ny, seed=8, planar=planar), 3,
+                                tau_ref=0.03)
+    assert info['planar'] == int(planar)
 
 
 # ------------------------------------------------------------------ full size
@@ -257,18 +270,20 @@ def test_full_size_cfl_time_step(gpu_lib):
     assert abs(info['dt_last'] - dt) < 1e-13 * dt
 
 
-def test_full_size_periodic_conservation(gpu_lib):
+@pytest.mark.parametrize('planar', [False, True])
+def test_full_size_periodic_conservation(gpu_lib, planar):
     """Sum rho, sum rho u_i, sum tr E are conserved with periodic boundaries (BGK conserves
-    them, fluxes telescope) at 2048^2 after a few steps."""
+    them, fluxes telescope) at 2048^2 after a few steps, with the full and the planar kernel."""
     n = 2048
     kw = dict(JETS, nx=n, ny=n, bc=('periodic',) * 4, jets=[])
-    W0 = I.random_smooth_field14(n, n, seed=12)
+    W0 = I.random_smooth_field14(n, n, seed=12, planar=planar)
     U0 = mo.prim_to_cons14(W0)
     Ug, info = gpu_run(gpu_lib, kw, W0, 3, tau_ref=0.02)
+    assert info['planar'] == int(planar)
     for comp in ([0], [1], [2], [3], [4, 7, 9]):
         a = U0[comp].sum()
         b = Ug[comp].sum()
-        assert abs(a - b) < 1e-12 * np.abs(U0[comp]).sum(), comp
+        assert abs(a - b) <= 1e-12 * np.abs(U0[comp]).sum(), comp
 
 
 # ------------------------------------------------------------------ behaviour
@@ -345,3 +360,58 @@ def test_oversized_fixed_dt_reports_failure_step(gpu_lib):
     assert info['status'] in ('NONFINITE', 'UNREALIZABLE')
     assert info['fail_step'] == 1
     s.close()
+
+
+# ------------------------------------------------------------------ planar symmetry
+def test_planar_detection(gpu_lib):
+    """The planar kernel runs only on 2D 14-moment states with u_z = P_xz = P_yz = q_z = 0 in
+    every cell: one cell with u_z != 0 (or any other z-odd moment) selects the full kernel."""
+    nx, ny = 40, 36
+    kw = dict(JETS, nx=nx, ny=ny)
+    W0 = I.crossed_jets_developed(nx, ny, seed=1)
+    for v, expect in ((None, 1), (3, 0), (6, 0), (8, 0), (12, 0)):
+        W = W0.copy()
+        if v is not None:
+            W[v, 17, 23] = 1e-9 * (1.0 if v != 6 and v != 8 else W[4, 17, 23])
+        _, info = gpu_run(gpu_lib, kw, W, 1, tau_ref=TAU_JET)
+        assert info['planar'] == expect, v
+    # 1D and 5-moment solvers never use it
+    _, info = gpu_run(gpu_lib, SOD14, I.sod_prims(14, 200), 1, tau_ref=TAU_SOD)
+    assert info['planar'] == 0
+
+
+def test_planar_pingpong_after_a_nonplanar_state(gpu_lib):
+    """Forward Euler ping-pongs between two buffers; the planar kernel never writes the z-odd
+    planes, so a solver that first ran a 3D state and then loads a planar one must still hand
+    back zero z-odd moments after an odd number of steps, equal to a fresh solver's result."""
+    nx, ny = 48, 40
+    kw = dict(JETS, nx=nx, ny=ny, order=2, integrator='fe', cfl=0.4, limiter='vanalbada',
+              bc=('periodic', 'periodic', 'periodic', 'periodic'), jets=[])
+    s = gpu_lib.MaxEntSolver(**kw)
+    try:
+        s.init_state(I.random_smooth_field14(nx, ny, seed=4))
+        info = s.step(3, tau_ref=0.05)
+        assert info['planar'] == 0
+        Wp = I.random_smooth_field14(nx, ny, seed=5, planar=True)
+        s.init_state(Wp)
+        info = s.step(3, tau_ref=0.05)
+        assert info['planar'] == 1
+        U1 = s.get('conserved').cpu().numpy()
+    finally:
+        s.close()
+    U2, info2 = gpu_run(gpu_lib, kw, Wp, 3, tau_ref=0.05)
+    assert np.all(U1[[3, 6, 8, 12]] == 0.0)
+    assert np.array_equal(U1, U2)
+
+
+def test_planar_mode_is_fixed_while_a_tape_is_recorded(gpu_lib):
+    nx, ny = 32, 32
+    s = gpu_lib.MaxEntSolver(**dict(JETS, nx=nx, ny=ny))
+    try:
+        s.init_state(I.crossed_jets_initial(nx, ny))
+        s.record(2, 8)
+        with pytest.raises(gpu_lib.MaxentError):
+            s.set_planar(False)
+        s.set_planar(True)          # unchanged: allowed
+    finally:
+        s.close()

@@ -55,6 +55,7 @@ def check_same(S, kw, U0, n, **k):
     Uh, ih = handle(S, kw, U0, n, **k)
     assert rc == 0, S.load_library().maxent_last_error(None)
     assert info['steps'] == ih['steps'] and info['t'] == ih['t'] and info['dt_last'] == ih['dt_last']
+    assert info['planar'] == ih['planar']
     assert np.array_equal(Un, Uh)
     return info
 
@@ -75,6 +76,21 @@ def test_forward_euler_odd_steps_and_fixed_dt(gpu_lib):
     check_same(gpu_lib, kw, U0, 4, dt=2e-4, tau_ref=0.01, t_end=5e-4)
     kw5 = dict(system=5, dim=1, nx=1000, order=1, integrator='fe', flux='hll', cfl=0.5)
     check_same(gpu_lib, kw5, mo.prim_to_cons5(I.sod_prims(5, 1000)).reshape(5, 1, 1000), 5, tau_ref=0.01)
+
+
+def test_planar_forward_euler_after_a_nonplanar_call(gpu_lib):
+    """A 3D state leaves non-zero z-odd planes in the scratch state; a following planar call
+    (planar kernel, which never writes those planes) with an odd forward-Euler step count
+    copies its result back from the scratch: its z-odd moments must still be zero."""
+    kw = dict(JETS, nx=48, ny=40, integrator='fe', limiter='vanalbada', bc=('periodic',) * 4, jets=[])
+    i1 = check_same(gpu_lib, kw, mo.prim_to_cons14(I.random_smooth_field14(48, 40, seed=4)), 3,
+                    tau_ref=0.05)
+    assert i1['planar'] == 0
+    Up = mo.prim_to_cons14(I.random_smooth_field14(48, 40, seed=5, planar=True))
+    i2 = check_same(gpu_lib, kw, Up, 3, tau_ref=0.05)
+    assert i2['planar'] == 1
+    rc, Un, _ = noalloc(gpu_lib, kw, Up, 3, tau_ref=0.05)
+    assert rc == 0 and np.all(Un[[3, 6, 8, 12]] == 0.0)
 
 
 def test_too_large_and_unrealizable_inputs(gpu_lib):
