@@ -27,11 +27,19 @@
 //   4. adj_reduce_kernel: sum the per-workgroup parameter partials in a fixed order.
 // No atomics: the result is bitwise reproducible.  Faces whose flux adjoint is exactly zero
 // (outside the adjoint's domain of dependence) skip the closure reverse.
+//
+// Planar runs (template flag PL): when the recorded states are planar-symmetric (u_z = P_xz
+// = P_yz = q_z = 0) and so is dJ/dU, the adjoint's z-odd components stay exactly zero too
+// (at a planar state the step's Jacobian does not couple z-even and z-odd moments), so the
+// kernels read those four components as the constant 0 and never store them.  The file is
+// compiled without signed zeros, NaN or infinity (these runs have none), which lets the
+// compiler drop every product with such a constant: the same reverse code on ten moments.
 #include "mx_internal.hpp"
 #include "mx_adjoint_params.hpp"
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
 #include "mx_bc.hpp"
+#include "mx_planar.hpp"
 #include "mx_adjoint.hpp"
 
 namespace mx {
@@ -62,25 +70,44 @@ __device__ __forceinline__ long long ext_idx(const AdjParams& a, int c, int l) {
   return (long long)(c + 2) * a.epitch + (l + 2);
 }
 
+// the z-odd moments of the 14-moment state (u_z, P_xz, P_yz, q_z)
+__device__ constexpr bool zodd(int v) { return v == 3 || v == 6 || v == 8 || v == 12; }
+
+// value of component v at index k of a 14-plane field, the constant 0 for a z-odd component
+// of a planar run
+template <bool PL>
+__device__ __forceinline__ double ld(const double* f, int v, long long stride, long long k) {
+  return (PL && zodd(v)) ? 0.0 : f[v * stride + k];
+}
+
+template <bool PL>
 __device__ __forceinline__ void get_w(const AdjParams& a, long long e, double* W) {
 #pragma unroll
-  for (int v = 0; v < 14; ++v) W[v] = a.wext[v * a.eplane + e];
+  for (int v = 0; v < 14; ++v) W[v] = ld<PL>(a.wext, v, a.eplane, e);
 }
 
 // ------------------------------------------------------------------ 0. prep
-template <int DIM>
+template <int DIM, bool PL>
 __global__ __launch_bounds__(ADJ_NT) void adj_prim_kernel(AdjParams a) {
   const long long e = xcd_block() * ADJ_NT + threadIdx.x;
   if (e >= a.eplane) return;
   const int i = (int)(e % a.epitch) - 2;
   const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
-  double W[14];
-  load_prims<Sys14>(a.sp, a.sp.Ub, i, j, W);
+  if constexpr (PL) {
+    // the planar forward kernel's primitive recovery (the recorded stages ran it)
+    double W[10];
+    load_prims<Sys14P>(a.sp, a.sp.Ub, i, j, W);
 #pragma unroll
-  for (int v = 0; v < 14; ++v) a.wext[v * a.eplane + e] = W[v];
+    for (int v = 0; v < 10; ++v) a.wext[Sys14P::plane_of(v) * a.eplane + e] = W[v];
+  } else {
+    double W[14];
+    load_prims<Sys14>(a.sp, a.sp.Ub, i, j, W);
+#pragma unroll
+    for (int v = 0; v < 14; ++v) a.wext[v * a.eplane + e] = W[v];
+  }
 }
 
-template <int DIM>
+template <int DIM, bool PL>
 __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
   const StageParams& p = a.sp;
   const long long e = xcd_block() * ADJ_NT + threadIdx.x;
@@ -91,9 +118,9 @@ __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
   double phi = 0.0;
   int vs = -1;
   if (j >= 0 && j < p.ny && i >= -1 && i <= p.nx) {
-    get_w(a, e - 1, Wm);
-    get_w(a, e, Wc);
-    get_w(a, e + 1, Wp);
+    get_w<PL>(a, e - 1, Wm);
+    get_w<PL>(a, e, Wc);
+    get_w<PL>(a, e + 1, Wp);
     phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
   }
   a.phix[e] = phi;
@@ -102,9 +129,9 @@ __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
     phi = 0.0;
     vs = -1;
     if (i >= 0 && i < p.nx && j >= -1 && j <= p.ny) {
-      get_w(a, e - a.epitch, Wm);
-      get_w(a, e, Wc);
-      get_w(a, e + a.epitch, Wp);
+      get_w<PL>(a, e - a.epitch, Wm);
+      get_w<PL>(a, e, Wc);
+      get_w<PL>(a, e + a.epitch, Wp);
       phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
     }
     a.phiy[e] = phi;
@@ -113,7 +140,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
 }
 
 // ------------------------------------------------------------------ 1. faces
-template <int D, int DIM, int ORDER>
+template <int D, int DIM, int ORDER, bool PL>
 __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
   // lanes 2k and 2k+1 own the left and the right state of face k; the grid has two threads
   // per face, so both lanes of a pair pass or fail every face-uniform test together
@@ -141,15 +168,16 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
     bool hl = fc - 1 >= 0, hr = fc < n;
 #pragma unroll
     for (int v = 0; v < 14; ++v) {
-      double ml = hl ? mc * a.lam_out[v * p.plane + cl] : 0.0;
-      double mr = hr ? mc * a.lam_out[v * p.plane + cr] : 0.0;
+      double ml = hl ? mc * ld<PL>(a.lam_out, v, p.plane, cl) : 0.0;
+      double mr = hr ? mc * ld<PL>(a.lam_out, v, p.plane, cr) : 0.0;
       Fhb[v] = (mr - ml) * inv_h;
       any = any || (Fhb[v] != 0.0);
     }
   }
   if (!any) {
 #pragma unroll
-    for (int v = 0; v < 14; ++v) out[v * nf] = 0.0;
+    for (int v = 0; v < 14; ++v)
+      if (!(PL && zodd(v))) out[v * nf] = 0.0;
     return;
   }
   // this lane's face state: the left state is the upper face state of cell fc-1, the right
@@ -160,13 +188,13 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
     const long long ec = ext_idx<D, DIM>(a, cc, l);
     const long long st = (D == 0) ? 1 : a.epitch;
     double Sm[14], Sc[14], Sp[14];
-    get_w(a, ec - st, Sm);
-    get_w(a, ec, Sc);
-    get_w(a, ec + st, Sp);
+    get_w<PL>(a, ec - st, Sm);
+    get_w<PL>(a, ec, Sc);
+    get_w<PL>(a, ec + st, Sp);
     const double ph = (D == 0) ? a.phix[ec] : a.phiy[ec];
     face_state<Sys14>(Sm, Sc, Sp, ph, right ? -1.0 : 1.0, W);
   } else {
-    get_w(a, ext_idx<D, DIM>(a, cc, l), W);
+    get_w<PL>(a, ext_idx<D, DIM>(a, cc, l), W);
   }
   // forward face terms (Sys14::face_terms, step by step): the closure core and closing values
   // are kept for the reverse below
@@ -198,13 +226,14 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
   if (any2) Adj14::face_terms_vjp_prepared<D>(k, Qd, Rd, Sd, W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
 #pragma unroll
-  for (int v = 0; v < 14; ++v) out[v * nf] = Wb[v];
+  for (int v = 0; v < 14; ++v)
+    if (!(PL && zodd(v))) out[v * nf] = Wb[v];
 }
 
 // ------------------------------------------------------------------ 2. extended cells
 // adjoint of the primitive state of cell c (line l, direction D) through the reconstruction
 // of the stencil cells c-1, c, c+1
-template <int D, int DIM, int ORDER>
+template <int D, int DIM, int ORDER, bool PL>
 __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, double* Wb) {
   const StageParams& p = a.sp;
   const int n = (D == 0) ? p.nx : p.ny;
@@ -219,11 +248,11 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
     // (as its left state)
     if (c >= 0 && c <= n) {
 #pragma unroll
-      for (int v = 0; v < 14; ++v) Wb[v] += fb[(14 + v) * nfs + fidx(c)];
+      for (int v = 0; v < 14; ++v) Wb[v] += ld<PL>(fb, 14 + v, nfs, fidx(c));
     }
     if (c + 1 >= 0 && c + 1 <= n) {
 #pragma unroll
-      for (int v = 0; v < 14; ++v) Wb[v] += fb[v * nfs + fidx(c + 1)];
+      for (int v = 0; v < 14; ++v) Wb[v] += ld<PL>(fb, v, nfs, fidx(c + 1));
     }
   } else {
     // stencil cells k = c-1, c, c+1 with face states (k in [-1, n]); each stencil's three
@@ -239,16 +268,16 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
       bool any = false;
 #pragma unroll
       for (int v = 0; v < 14; ++v) {
-        Op[v] = (k + 1 <= n) ? fb[v * nfs + fidx(k + 1)] : 0.0;        // upper face: its WL
-        Om[v] = (k >= 0) ? fb[(14 + v) * nfs + fidx(k)] : 0.0;         // lower face: its WR
+        Op[v] = (k + 1 <= n) ? ld<PL>(fb, v, nfs, fidx(k + 1)) : 0.0;        // upper face: its WL
+        Om[v] = (k >= 0) ? ld<PL>(fb, 14 + v, nfs, fidx(k)) : 0.0;          // lower face: its WR
         any = any || Op[v] != 0.0 || Om[v] != 0.0;
       }
       if (!any) continue;
       const long long ek = e0 + (r - 1) * st;
       double Sm[14], Sc[14], Sp[14];
-      get_w(a, ek - st, Sm);
-      get_w(a, ek, Sc);
-      get_w(a, ek + st, Sp);
+      get_w<PL>(a, ek - st, Sm);
+      get_w<PL>(a, ek, Sc);
+      get_w<PL>(a, ek + st, Sp);
       const double phi = (D == 0) ? a.phix[ek] : a.phiy[ek];
       const int vstar = (D == 0) ? a.vsx[ek] : a.vsy[ek];
       // cell c is the stencil's Wp (r = 0), Wc (r = 1) or Wm (r = 2)
@@ -257,7 +286,7 @@ __device__ __forceinline__ void gather_line(const AdjParams& a, int c, int l, do
   }
 }
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, bool PL>
 __global__ __launch_bounds__(ADJ_NT) void adj_cell_kernel(AdjParams a) {
   const StageParams& p = a.sp;
   const long long e = xcd_block() * ADJ_NT + threadIdx.x;
@@ -270,16 +299,17 @@ __global__ __launch_bounds__(ADJ_NT) void adj_cell_kernel(AdjParams a) {
 #pragma unroll
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
   const bool in_i = i >= 0 && i < p.nx, in_j = j >= 0 && j < p.ny;
-  if (in_j) gather_line<0, DIM, ORDER>(a, i, j, Wb);
+  if (in_j) gather_line<0, DIM, ORDER, PL>(a, i, j, Wb);
   if constexpr (DIM == 2) {
-    if (in_i) gather_line<1, DIM, ORDER>(a, j, i, Wb);
+    if (in_i) gather_line<1, DIM, ORDER, PL>(a, j, i, Wb);
   }
 #pragma unroll
-  for (int v = 0; v < 14; ++v) a.wb[v * a.eplane + e] = Wb[v];
+  for (int v = 0; v < 14; ++v)
+    if (!(PL && zodd(v))) a.wb[v * a.eplane + e] = Wb[v];
 }
 
 // ------------------------------------------------------------------ 3. interior cells
-template <int DIM>
+template <int DIM, bool PL>
 __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
   const StageParams& p = a.sp;
   __shared__ double sRed[3][ADJ_NT / 64];
@@ -295,7 +325,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
     double Wb[14];
     const long long e = (long long)ej * a.epitch + (i + 2);
 #pragma unroll
-    for (int v = 0; v < 14; ++v) Wb[v] = a.wb[v * a.eplane + e];
+    for (int v = 0; v < 14; ++v) Wb[v] = ld<PL>(a.wb, v, a.eplane, e);
     // a ghost cell holding a jet state: its adjoint goes to the jet parameters
     auto fold_jet = [&](int jet, long long eg) {
       double sn, cs;
@@ -304,7 +334,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
       const double c0 = sqrt(5.0 / 3.0 * T);
       double G[14];
 #pragma unroll
-      for (int v = 0; v < 14; ++v) G[v] = a.wb[v * a.eplane + eg];
+      for (int v = 0; v < 14; ++v) G[v] = ld<PL>(a.wb, v, a.eplane, eg);
       gM += (G[1] * cs + G[2] * sn) * c0;
       gR += G[0] + T * (G[4] + G[7] + G[9]) + 15.0 * T * T * G[13];
     };
@@ -326,7 +356,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
       }
 #pragma unroll
       for (int v = 0; v < 14; ++v) {
-        double gv = a.wb[v * a.eplane + eg];
+        double gv = ld<PL>(a.wb, v, a.eplane, eg);
         Wb[v] += (rx && Sys14::odd(v, 0)) ? -gv : gv;
       }
     }
@@ -348,7 +378,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
         }
 #pragma unroll
         for (int v = 0; v < 14; ++v) {
-          double gv = a.wb[v * a.eplane + eg];
+          double gv = ld<PL>(a.wb, v, a.eplane, eg);
           Wb[v] += (ry && Sys14::odd(v, 1)) ? -gv : gv;
         }
       }
@@ -357,8 +387,8 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
     double U[14], lo[14];
 #pragma unroll
     for (int v = 0; v < 14; ++v) {
-      U[v] = p.Ub[v * p.plane + off];
-      lo[v] = a.lam_out[v * p.plane + off];
+      U[v] = ld<PL>(p.Ub, v, p.plane, off);
+      lo[v] = ld<PL>(a.lam_out, v, p.plane, off);
     }
     if (p.use_source) {
       double W[14];
@@ -379,6 +409,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
     Adj14::cons_to_prim_vjp(U, Wb, Ubar);
 #pragma unroll
     for (int v = 0; v < 14; ++v) {
+      if (PL && zodd(v)) continue;
       double r = a.beta * lo[v] + Ubar[v];
       if (a.lam_extra) r += a.extra_coef * a.lam_extra[v * p.plane + off];
       a.lam_in[v * p.plane + off] = r;
@@ -451,24 +482,44 @@ int adjoint_update_blocks(int nx, int ny) {
   return (int)(((long long)nx * ny + ADJ_NT - 1) / ADJ_NT);
 }
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, bool PL>
 static hipError_t launch_adj_t(AdjParams& a, hipStream_t s) {
   auto blocks = [](long long n) { return dim3((unsigned)((n + ADJ_NT - 1) / ADJ_NT)); };
-  hipLaunchKernelGGL((adj_prim_kernel<DIM>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_prim_kernel<DIM, PL>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
   if constexpr (ORDER == 2)
-    hipLaunchKernelGGL((adj_limiter_kernel<DIM>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
-  hipLaunchKernelGGL((adj_face_kernel<0, DIM, ORDER>), blocks(2 * a.nfx), dim3(ADJ_NT), 0, s, a);
+    hipLaunchKernelGGL((adj_limiter_kernel<DIM, PL>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_face_kernel<0, DIM, ORDER, PL>), blocks(2 * a.nfx), dim3(ADJ_NT), 0, s, a);
   if constexpr (DIM == 2)
-    hipLaunchKernelGGL((adj_face_kernel<1, DIM, ORDER>), blocks(2 * a.nfy), dim3(ADJ_NT), 0, s, a);
-  hipLaunchKernelGGL((adj_cell_kernel<DIM, ORDER>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
-  hipLaunchKernelGGL((adj_update_kernel<DIM>), dim3(a.n_upd_blocks), dim3(ADJ_NT), 0, s, a);
+    hipLaunchKernelGGL((adj_face_kernel<1, DIM, ORDER, PL>), blocks(2 * a.nfy), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_cell_kernel<DIM, ORDER, PL>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_update_kernel<DIM, PL>), dim3(a.n_upd_blocks), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(ADJ_NT), 0, s, a.part, a.n_upd_blocks, a.grad);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_stage(int dim, int order, AdjParams& a, hipStream_t s) {
-  if (dim == 2) return order == 2 ? launch_adj_t<2, 2>(a, s) : launch_adj_t<2, 1>(a, s);
-  return order == 2 ? launch_adj_t<1, 2>(a, s) : launch_adj_t<1, 1>(a, s);
+hipError_t launch_adjoint_stage(int dim, int order, bool planar, AdjParams& a, hipStream_t s) {
+  if (dim == 2) {
+    if (planar) return order == 2 ? launch_adj_t<2, 2, true>(a, s) : launch_adj_t<2, 1, true>(a, s);
+    return order == 2 ? launch_adj_t<2, 2, false>(a, s) : launch_adj_t<2, 1, false>(a, s);
+  }
+  return order == 2 ? launch_adj_t<1, 2, false>(a, s) : launch_adj_t<1, 1, false>(a, s);
+}
+
+// nonzero z-odd component (3, 6, 8, 12) in a flat 14-moment field of n cells: ctrl->nonplanar
+__global__ __launch_bounds__(256) void check_planar_kernel(const double* f, long long n, DevCtrl* c) {
+  int np = 0;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256)
+    np |= (f[3 * n + k] != 0.0 || f[6 * n + k] != 0.0 || f[8 * n + k] != 0.0 || f[12 * n + k] != 0.0);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) np |= __shfl_xor(np, o, 64);
+  if ((threadIdx.x & 63) == 0 && np) atomicOr(&c->nonplanar, 1);
+}
+
+hipError_t launch_check_planar(const double* f, long long n, DevCtrl* c, hipStream_t s) {
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(check_planar_kernel, dim3(grid), dim3(256), 0, s, f, n, c);
+  return hipGetLastError();
 }
 
 hipError_t launch_tape_dt(const DevCtrl* c, double* slot, hipStream_t s) {

@@ -823,18 +823,29 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   } catch (const std::bad_alloc&) {
     return fail(s, MAXENT_E_NOMEM, "host allocation failed");
   }
-  if (n > 0) {
+  if (n > 0)
     HIP_TRY(s, hipMemcpyAsync(dts.data(), t->d_dt, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
                               s->stream));
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
-  }
   // lambda <- dJ/dU_final
   const size_t flat = (size_t)s->nv * nx * ny * sizeof(double);
   HIP_TRY(s, hipMemcpyAsync(s->stage, dJ_dU, flat,
                             dJ_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+  // planar run: planar-symmetric recorded states (the planar kernels ran them) and a
+  // planar-symmetric dJ/dU keep the z-odd adjoint components at zero
+  int nonplanar = 1;
+  if (s->planar()) {
+    HIP_TRY(s, mx::launch_ctrl_reset(t->actrl, 0.0, s->stream));
+    HIP_TRY(s, mx::launch_check_planar(s->stage, (long long)nx * ny, t->actrl, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(&nonplanar, &t->actrl->nonplanar, sizeof(int), hipMemcpyDeviceToHost,
+                              s->stream));
+  }
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  const bool pl = s->planar() && nonplanar == 0;
   double* lamA = t->lam[0];
   double* lamB = t->lam[1];
   double* lamC = t->lam[2];
+  if (pl)  // never written in a planar run: they start (and stay) zero
+    for (double* l : {lamA, lamB, lamC}) HIP_TRY(s, mx::launch_zero_planes(l, s->plane, 14, s->stream));
   HIP_TRY(s, mx::launch_pad_copy(s->stage, lamA, s->nv, nx, ny, s->pitch, 1, s->stream));
   HIP_TRY(s, hipMemsetAsync(t->grad, 0, 3 * sizeof(double), s->stream));
 
@@ -910,19 +921,19 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
         a.sp.Ub = segU[j];
         a.lam_out = lamA; a.lam_extra = nullptr; a.extra_coef = 0.0;
         a.beta = 1.0; a.mu_coef = 1.0; a.lam_in = lamC;
-        HIP_TRY(s, mx::launch_adjoint_stage(dim, ord, a, s->stream));
+        HIP_TRY(s, mx::launch_adjoint_stage(dim, ord, pl, a, s->stream));
       } else {
         const bool mid = integ == MAXENT_MIDPOINT;
         // second stage: Uout = alpha U^n + beta U* + mu dt L(U*)
         a.sp.Ub = segS[j];
         a.lam_out = lamA; a.lam_extra = nullptr; a.extra_coef = 0.0;
         a.beta = mid ? 0.0 : 0.5; a.mu_coef = mid ? 1.0 : 0.5; a.lam_in = lamB;
-        HIP_TRY(s, mx::launch_adjoint_stage(dim, ord, a, s->stream));
+        HIP_TRY(s, mx::launch_adjoint_stage(dim, ord, pl, a, s->stream));
         // first stage: U* = U^n + cdt dt L(U^n); U^n also enters the second stage with alpha
         a.sp.Ub = segU[j];
         a.lam_out = lamB; a.lam_extra = lamA; a.extra_coef = mid ? 1.0 : 0.5;
         a.beta = 1.0; a.mu_coef = cdt1; a.lam_in = lamC;
-        HIP_TRY(s, mx::launch_adjoint_stage(dim, ord, a, s->stream));
+        HIP_TRY(s, mx::launch_adjoint_stage(dim, ord, pl, a, s->stream));
       }
       std::swap(lamA, lamC);
     }
