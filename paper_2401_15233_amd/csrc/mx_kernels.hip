@@ -43,9 +43,9 @@ __device__ __forceinline__ int wave_sum(int v) {
 
 // ------------------------------------------------------------------ stage kernel
 // Waves per SIMD the kernel is compiled for.  The planar 2D kernel (ten moments) fits three
-// 256-thread workgroups per CU in LDS (45 KB each, with the x-face fluxes kept in registers);
-// asking for three waves per SIMD caps it at 168 VGPRs, a few of them spilled, which measured
-// faster than two waves without spills.  The full 14-moment kernel needs two.
+// 256-thread workgroups per CU in LDS (45 KB each, with part of the x-face fluxes kept in
+// registers); asking for three waves per SIMD caps it at 168 VGPRs, a few of them spilled,
+// which measured faster than two waves without spills.  The full 14-moment kernel needs two.
 constexpr int stage_min_waves(int nv, int dim) { return (nv <= 10 && dim == 2) ? 3 : 1; }
 
 template <class SYS, int DIM, int ORDER, int PREC, int TX, int TY, int NT>
@@ -60,12 +60,17 @@ void stage_kernel(StageParams p) {
   constexpr int NFY = (DIM == 2) ? TX * (TY + 1) : 0;
   constexpr int NPX = (ORDER == 2) ? (TX + 2) * TY : 1;
   constexpr int NPY = (ORDER == 2 && DIM == 2) ? TX * (TY + 2) : 1;
-  // planar 2D: the x-face fluxes stay in registers with the y-face fluxes and both overwrite
-  // the primitive tile after a barrier (no separate x-flux array: 45 KB of LDS per workgroup,
-  // three workgroups per CU)
+  // planar 2D (XREG): no separate x-flux array (45 KB of LDS per workgroup, three workgroups
+  // per CU).  The x-flux components v >= XK go to LDS at once, past the primitive tile (free
+  // during the face phases); the first XK stay in registers with the y-face fluxes and all of
+  // them overwrite the primitive tile after a barrier
   constexpr bool XREG = (DIM == 2 && NV <= 10);
   constexpr int NFL = XREG ? NV * (NFX + NFY) : NV * NFY;
   constexpr int NW = (NV * NL > NFL) ? NV * NL : NFL;
+  constexpr int XK = XREG ? NV - (NW - NV * NL) / NFX : NV;
+  constexpr int XH = NW - (NV - XK) * NFX;      // where the LDS-held x-flux components start
+  static_assert(!XREG || XH >= NV * NL, "x-flux slots past the primitive tile");
+  static_assert(!XREG || XK * NFX + NV * NFY <= XH, "fluxes after the barrier fit below them");
   static_assert(NFX <= NT || DIM == 1, "one x-face per thread");
 
   __shared__ double sW[NW];        // primitives of the tile + halo; later the face fluxes
@@ -182,7 +187,10 @@ void stage_kernel(StageParams p) {
     nstates += 2;
     if constexpr (XREG) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fx[v] = Fh[v];
+      for (int v = 0; v < NV; ++v) {
+        if (v < XK) Fx[v] = Fh[v];
+        else sW[XH + (v - XK) * NFX + f] = Fh[v];
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) sFx[v * NFX + f] = Fh[v];
@@ -243,13 +251,13 @@ void stage_kernel(StageParams p) {
   }
   __syncthreads();
   // y-face fluxes (and, planar, the x-face fluxes) over the primitive tile
-  constexpr int Y0 = XREG ? NV * NFX : 0;
+  constexpr int Y0 = XREG ? XK * NFX : 0;
   if constexpr (DIM == 2) {
     if constexpr (XREG) {
       static_assert(NFX <= NT, "one x-face per thread");
       if (t < NFX) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sW[v * NFX + t] = Fx[v];
+        for (int v = 0; v < XK; ++v) sW[v * NFX + t] = Fx[v];
       }
     }
     if (has_y) {
@@ -268,7 +276,8 @@ void stage_kernel(StageParams p) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double* fx = XREG ? sW : sFx;
-        double L = -(fx[v * NFX + cj * (TX + 1) + ci + 1] - fx[v * NFX + cj * (TX + 1) + ci]) * p.inv_dx;
+        const int xb = (XREG && v >= XK) ? XH + (v - XK) * NFX : v * NFX;
+        double L = -(fx[xb + cj * (TX + 1) + ci + 1] - fx[xb + cj * (TX + 1) + ci]) * p.inv_dx;
         if constexpr (DIM == 2)
           L = L - (sW[Y0 + v * NFY + (cj + 1) * TX + ci] - sW[Y0 + v * NFY + cj * TX + ci]) * p.inv_dy;
         L = L + Cs[v];
