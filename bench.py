@@ -267,11 +267,14 @@ def batch_record(stream, steps=5000, chunk=500):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        reduced = int(b.info()['reduced'])
         b.close()
         rec = {'steps': steps, 'ms': ms, 'cell_updates': info['cell_updates'],
                'value': info['cell_updates'] / (ms / 1e3), 'unit': 'cell-updates/s',
                'launch': {k: tuned[k] for k in ('threads', 'cells_per_thread', 'wg_per_cu')},
-               'active_instances_after': info['n_active']}
+               'active_instances_after': info['n_active'],
+               # 2: the tubes are axially symmetric and the axial kernel (seven moments) runs
+               'reduced_kernel': reduced}
         if prec == 'mixed':
             rec['fp64_reevaluated_face_state_fraction'] = \
                 info['n_fp64_states'] / max(info['n_face_states'], 1)
@@ -421,7 +424,7 @@ def sod_gpu_record(stream, steps1=500):
     s.close()
     out['sod14_20000_kn0.01'] = {'steps': info['steps'], 'ms': ms, 'us_per_step': 1e3 * ms / info['steps'],
                                  'cell_updates_per_s': 20000 * info['steps'] / (ms / 1e3),
-                                 'status': info['status']}
+                                 'status': info['status'], 'reduced_kernel': int(info['reduced'])}
     return out
 
 
@@ -463,7 +466,7 @@ def full_run_record(stream, n, steps=2000):
     return {'workload': f'{n}x{n} crossed jets, all {steps} steps from rest',
             'fp64': {'value': n * n * info64['steps'] / (ms64 / 1e3), 'unit': 'cell-updates/s',
                      'ms_per_step': ms64 / max(info64['steps'], 1), 'steps': info64['steps'],
-                     'status': info64['status'], 't': info64['t'], 'planar_kernel': bool(info64['planar'])},
+                     'status': info64['status'], 't': info64['t'], 'reduced_kernel': int(info64['reduced'])},
             'mixed': {'value': n * n * infomx['steps'] / (msmx / 1e3), 'unit': 'cell-updates/s',
                       'ms_per_step': msmx / max(infomx['steps'], 1), 'steps': infomx['steps'],
                       'status': infomx['status'], 'speedup_vs_fp64': ms64 / msmx,
@@ -574,7 +577,7 @@ def main():
         kw = jets_kwargs(n)
         kw['precision'] = precision
         s = solver.MaxEntSolver(stream=stream, **kw)
-        s.set_planar(planar)
+        s.set_reduced(planar)
         s.init_state(W0 if init is None else init)
         if a.advance:
             s.step(a.advance, tau_ref=tau)
@@ -599,7 +602,7 @@ def main():
     cells = n * n
     cups = cells * a.steps / (ms / 1e3)
     avg_stage_ms = stage_ms / max(launches, 1)
-    planar = bool(info.get('planar'))
+    planar = info.get('reduced') == 1
     bpc = PLANAR_BYTES_PER_CELL_STAGE if planar else BYTES_PER_CELL_STAGE
     fpc = PLANAR_FLOPS_PER_CELL_STAGE if planar else FLOPS_PER_CELL_STAGE
     bytes_per_launch = cells * 0.5 * (bpc[1] + bpc[2])

@@ -142,8 +142,9 @@ typedef struct {
                                 maxent_step                                          */
   double fp64_fraction;     /* share of face-state evaluations done in FP64: 1 for FP64,
                                n_fp64_states / n_face_states for MIXED, 0 for FP32      */
-  int planar;               /* 1: the 2D 14-moment state is planar-symmetric and the
-                               steps run the planar stage kernel (maxent_set_planar)    */
+  int reduced;              /* the stage kernels carry only the moments the state's
+                               symmetry leaves non-zero (maxent_set_reduced): 0 no,
+                               1 planar (2D, ten moments), 2 axial (1D, seven moments)  */
   int reserved;
 } maxent_info;
 
@@ -327,9 +328,9 @@ int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ_on_device,
  * device, held until the process ends), so a problem fits when
  *   256 + 8 * nv * nx * ny <= MAXENT_NOALLOC_SCRATCH_BYTES
  * (at most 599 184 cells with 14 moments, e.g. 768 x 768; 1 677 715 cells with 5); larger
- * problems are rejected with INVAL before any device work.  A planar-symmetric 2D
- * 14-moment state runs the planar stage kernel (maxent_set_planar's default); the call then
- * synchronises the stream once more, after checking the input.
+ * problems are rejected with INVAL before any device work.  A symmetric 14-moment state runs
+ * the reduced stage kernel (maxent_set_reduced's default); the call then synchronises the
+ * stream once more, after checking the input.
  *   U        the caller's device state, conserved, [nv][ny][nx] unpadded (the field-array
  *            layout above); read as the state at t0, overwritten with the state after the
  *            steps.  Checked first: a non-finite or unrealizable input returns NONFINITE /
@@ -347,18 +348,21 @@ int maxent_step_noalloc(const maxent_problem* problem, const maxent_numerics* nu
                         double* U, int n, double dt, double tau_ref, double t_end, double t0,
                         void* stream, maxent_info* info);
 
-/* Planar symmetry of the 2D 14-moment system (Section 2.4 equations in the x-y plane).  A
- * state whose distribution is even in the z velocity has u_z = P_xz = P_yz = q_z = 0 in
- * every cell, and the step keeps these four moments exactly zero (each of their fluxes,
- * closing moments and source terms carries a z-odd factor; jet inflow states lie in the
- * plane).  maxent_init_state checks the loaded state; when it is planar-symmetric and
- * planar mode is on (enable = 1, the default) the stage kernels carry only the ten other
- * moments: the same step up to the rounding order of the terms that remain, about 30 %
- * fewer operations and bytes.  enable = 0 always runs the full 14-moment kernel.  The mode
- * applies from the next maxent_step; maxent_info.planar reports which kernel runs.
- * Errors: INVAL (null handle), STATE (a tape is recorded: the recorded run and its
- * recomputation must use one kernel). */
-int maxent_set_planar(maxent_solver* s, int enable);
+/* Symmetry-reduced kernels of the 14-moment system (Section 2.4 equations).
+ *   2D planar: a state whose distribution is even in the z velocity has u_z = P_xz = P_yz =
+ *     q_z = 0 in every cell, and the step keeps these four moments exactly zero (each of
+ *     their fluxes, closing moments and source terms carries a z-odd factor; jet inflow
+ *     states lie in the plane); the stage kernels then carry the ten other moments.
+ *   1D axial (single solvers and batched tubes): a state also even in the y velocity has, in
+ *     addition, u_y = P_xy = q_y = 0, kept zero by the x-direction step; the stage kernels
+ *     then carry seven moments (rho, u_x, P_xx, P_yy, P_zz, q_x, R).
+ * maxent_init_state checks the loaded state; with the mode on (enable = 1, the default) a
+ * symmetric state runs the reduced kernel: the same step up to the rounding order of the
+ * terms that remain, with 35 % (planar) or more (axial) fewer operations and bytes.
+ * enable = 0 always runs the full 14-moment kernels.  The mode applies from the next step;
+ * maxent_info.reduced reports which kernel runs.  Errors: INVAL (null handle), STATE (a tape
+ * is recorded: the recorded run and its recomputation must use one kernel). */
+int maxent_set_reduced(maxent_solver* s, int enable);
 
 /* Optional timing of the fused stage kernels: when enabled, every stage-kernel launch of
  * maxent_step is bracketed by HIP events on the solver's stream and the elapsed times are

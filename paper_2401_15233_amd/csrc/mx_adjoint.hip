@@ -505,14 +505,14 @@ hipError_t launch_adjoint_stage(int dim, int order, bool planar, AdjParams& a, h
   return order == 2 ? launch_adj_t<1, 2, false>(a, s) : launch_adj_t<1, 1, false>(a, s);
 }
 
-// nonzero z-odd component (3, 6, 8, 12) in a flat 14-moment field of n cells: ctrl->nonplanar
+// nonzero z-odd component (3, 6, 8, 12) in a flat 14-moment field of n cells: ctrl->asym
 __global__ __launch_bounds__(256) void check_planar_kernel(const double* f, long long n, DevCtrl* c) {
   int np = 0;
   for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256)
     np |= (f[3 * n + k] != 0.0 || f[6 * n + k] != 0.0 || f[8 * n + k] != 0.0 || f[12 * n + k] != 0.0);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) np |= __shfl_xor(np, o, 64);
-  if ((threadIdx.x & 63) == 0 && np) atomicOr(&c->nonplanar, 1);
+  if ((threadIdx.x & 63) == 0 && np) atomicOr(&c->asym, ASYM_Z);
 }
 
 hipError_t launch_check_planar(const double* f, long long n, DevCtrl* c, hipStream_t s) {

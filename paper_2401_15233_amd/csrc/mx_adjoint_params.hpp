@@ -40,7 +40,8 @@ struct AdjParams {
 // planar: the recorded states and dJ/dU are planar-symmetric (2D only): the z-odd adjoint
 // components are zero and are neither read nor written
 hipError_t launch_adjoint_stage(int dim, int order, bool planar, AdjParams& a, hipStream_t s);
-// sets ctrl->nonplanar when a z-odd component of the flat 14-moment field f (n cells) is nonzero
+// sets ASYM_Z in ctrl->asym when a z-odd component of the flat 14-moment field f (n cells) is
+// nonzero
 hipError_t launch_check_planar(const double* f, long long n, DevCtrl* c, hipStream_t s);
 int adjoint_update_blocks(int nx, int ny);
 hipError_t launch_tape_dt(const DevCtrl* c, double* slot, hipStream_t s);

@@ -90,11 +90,16 @@ struct maxent_solver {
   BatchState* batch = nullptr;
   TapeState* tape = nullptr;
   int adj_mode = MAXENT_ADJ_EXACT;
-  bool planar_state = false;  // the loaded state is planar-symmetric (checked by the ingest)
-  bool planar_on = true;      // maxent_set_planar
+  int asym = mx::ASYM_Z | mx::ASYM_Y;  // symmetry of the loaded state (set by the ingest)
+  bool reduced_on = true;               // maxent_set_reduced
   std::string err;
-  // the 2D 14-moment stage kernels run on the ten planar moments
-  bool planar() const { return planar_state && planar_on && prob.system == 14 && prob.dim == 2; }
+  // the 14-moment stage kernels carry only the moments the state's symmetry leaves non-zero:
+  // 2D planar (no z-odd moment; ten moments), 1D axial (no y- or z-odd moment; seven)
+  bool reduced() const {
+    if (!reduced_on || prob.system != 14) return false;
+    return prob.dim == 2 ? (asym & mx::ASYM_Z) == 0 : asym == 0;
+  }
+  bool planar() const { return reduced() && prob.dim == 2; }
 };
 
 // message of the last failed call without a handle (maxent_create, maxent_create_batch,
@@ -300,7 +305,7 @@ static int stage_precision(const maxent_numerics& n) {
 
 static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::StageParams& p) {
   const int prec = stage_precision(s->num);
-  if (!s->prof) return mx::launch_stage(sys, dim, ord, prec, s->planar(), p, s->stream);
+  if (!s->prof) return mx::launch_stage(sys, dim, ord, prec, s->reduced(), p, s->stream);
   while (s->ev.size() < s->ev_used + 2) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
@@ -313,7 +318,7 @@ static hipError_t stage(maxent_solver* s, int sys, int dim, int ord, const mx::S
     }
   }
   hipError_t r = hipEventRecord(s->ev[s->ev_used], s->stream);
-  if (r == hipSuccess) r = mx::launch_stage(sys, dim, ord, prec, s->planar(), p, s->stream);
+  if (r == hipSuccess) r = mx::launch_stage(sys, dim, ord, prec, s->reduced(), p, s->stream);
   if (r == hipSuccess) r = hipEventRecord(s->ev[s->ev_used + 1], s->stream);
   s->ev_used += 2;
   return r;
@@ -360,7 +365,7 @@ static void fill_info(maxent_solver* s, maxent_info* info) {
   info->n_sigma_limited = -1;     // counted by maxent_get_info only
   info->fp64_fraction = c.n_states > 0 ? (double)c.n_fp64 / (double)c.n_states
                                        : (s->num.precision == MAXENT_FP64 ? 1.0 : 0.0);
-  info->planar = s->planar() ? 1 : 0;
+  info->reduced = s->reduced() ? (s->prob.dim == 2 ? 1 : 2) : 0;
   info->reserved = 0;
 }
 
@@ -440,12 +445,12 @@ extern "C" int maxent_init_state(maxent_solver* s, int repr, const double* src, 
   } else {
     HIP_TRY(s, run_cfl(s));
   }
-  // the planar kernels never write the z-odd planes: the stage / ping-pong buffer starts
-  // from zeros so that a forward-Euler swap hands back a planar state
+  // the reduced kernels never write the moments they leave out: the stage / ping-pong buffer
+  // starts from zeros there, so that a forward-Euler swap hands back a symmetric state
   HIP_TRY(s, mx::launch_zero_planes(s->Us, s->plane, s->nv, s->stream));
   int rc = read_ctrl(s);
   if (rc) return rc;
-  s->planar_state = s->prob.system == 14 && s->ctrl_host->nonplanar == 0;
+  s->asym = s->ctrl_host->asym;
   s->ready = true;
   s->rate_valid = true;
   int st = s->ctrl_host->status;
@@ -606,14 +611,14 @@ extern "C" int maxent_step_noalloc(const maxent_problem* problem, const maxent_n
   e = mx::launch_ctrl_reset(t.ctrl, t0, t.stream);
   if (e == hipSuccess)
     e = mx::launch_ingest(nv, MAXENT_CONSERVED, U, U, problem->nx, problem->ny, problem->nx, t.ctrl, t.stream);
-  // planar symmetry of a 2D 14-moment state: read the ingest's flag, and give the scratch
-  // state zero z-odd planes (the planar kernels never write them)
-  if (e == hipSuccess && nv == 14 && problem->dim == 2) {
-    int nonplanar = 1;
-    e = hipMemcpyAsync(&nonplanar, &t.ctrl->nonplanar, sizeof(int), hipMemcpyDeviceToHost, t.stream);
+  // symmetry of a 14-moment state: read the ingest's flags, and give the scratch state zero
+  // planes where a reduced kernel writes none
+  if (e == hipSuccess && nv == 14) {
+    int asym = mx::ASYM_Z | mx::ASYM_Y;
+    e = hipMemcpyAsync(&asym, &t.ctrl->asym, sizeof(int), hipMemcpyDeviceToHost, t.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(t.stream);
-    t.planar_state = e == hipSuccess && nonplanar == 0;
-    if (e == hipSuccess && t.planar_state) e = mx::launch_zero_planes(t.Us, t.plane, nv, t.stream);
+    if (e == hipSuccess) t.asym = asym;
+    if (e == hipSuccess && t.reduced()) e = mx::launch_zero_planes(t.Us, t.plane, nv, t.stream);
   }
   if (e == hipSuccess) e = enqueue_steps(&t, n, dt, tau_ref, t_end);
   // FE ping-pongs: after an odd number of steps the state sits in the scratch
@@ -635,7 +640,7 @@ extern "C" int maxent_step_noalloc(const maxent_problem* problem, const maxent_n
     info->n_sigma_limited = -1;
     info->fp64_fraction = host.n_states > 0 ? (double)host.n_fp64 / (double)host.n_states
                                             : (numerics->precision == MAXENT_FP64 ? 1.0 : 0.0);
-    info->planar = t.planar() ? 1 : 0;
+    info->reduced = t.reduced() ? (problem->dim == 2 ? 1 : 2) : 0;
     info->reserved = 0;
   }
   if (host.status & mx::ST_NONFINITE) return noalloc_fail(MAXENT_E_NONFINITE, "non-finite cell state");
@@ -780,7 +785,7 @@ static hipError_t adjoint_workspace(maxent_solver* s) {
   if (e == hipSuccess) e = hipMalloc(&t->grad, 3 * sizeof(double));
   for (auto& p : t->lam)
     if (e == hipSuccess) e = hipMemsetAsync(p, 0, field, s->stream);
-  // the recomputed stage states: the planar kernels leave their z-odd planes as they are
+  // the recomputed stage states: the reduced kernels leave the moments they drop as they are
   for (auto& p : t->seg)
     if (e == hipSuccess) e = hipMemsetAsync(p, 0, field, s->stream);
   if (e == hipSuccess) e = hipMalloc(&t->actrl, sizeof(DevCtrl));
@@ -836,7 +841,7 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   if (s->planar()) {
     HIP_TRY(s, mx::launch_ctrl_reset(t->actrl, 0.0, s->stream));
     HIP_TRY(s, mx::launch_check_planar(s->stage, (long long)nx * ny, t->actrl, s->stream));
-    HIP_TRY(s, hipMemcpyAsync(&nonplanar, &t->actrl->nonplanar, sizeof(int), hipMemcpyDeviceToHost,
+    HIP_TRY(s, hipMemcpyAsync(&nonplanar, &t->actrl->asym, sizeof(int), hipMemcpyDeviceToHost,
                               s->stream));
   }
   HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -893,7 +898,7 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
         if (need_next) {
           p.Ub = segU[j]; p.Ua = segU[j]; p.Uout = outU;
           p.mode = mx::MODE_EULER; p.cdt = 1.0;
-          HIP_TRY(s, mx::launch_stage(14, dim, ord, 0, s->planar(), p, s->stream));
+          HIP_TRY(s, mx::launch_stage(14, dim, ord, 0, s->reduced(), p, s->stream));
         }
         segU[j + 1] = outU;
         continue;
@@ -901,13 +906,13 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
       double* outS = t->seg[(size_t)(K + j)];
       p.Ub = segU[j]; p.Ua = segU[j]; p.Uout = outS;
       p.mode = mx::MODE_EULER; p.cdt = cdt1;
-      HIP_TRY(s, mx::launch_stage(14, dim, ord, 0, s->planar(), p, s->stream));
+      HIP_TRY(s, mx::launch_stage(14, dim, ord, 0, s->reduced(), p, s->stream));
       segS[j] = outS;
       if (need_next) {
         p.Ub = outS; p.Ua = segU[j]; p.Uout = outU;
         p.mode = (integ == MAXENT_MIDPOINT) ? mx::MODE_MID2 : mx::MODE_HEUN2;
         p.cdt = 1.0;
-        HIP_TRY(s, mx::launch_stage(14, dim, ord, 0, s->planar(), p, s->stream));
+        HIP_TRY(s, mx::launch_stage(14, dim, ord, 0, s->reduced(), p, s->stream));
       }
       segU[j + 1] = outU;
     }
@@ -957,11 +962,11 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   return MAXENT_OK;
 }
 
-extern "C" int maxent_set_planar(maxent_solver* s, int enable) {
+extern "C" int maxent_set_reduced(maxent_solver* s, int enable) {
   if (!s) return MAXENT_E_INVAL;
-  if (s->tape && (enable != 0) != s->planar_on)
-    return fail(s, MAXENT_E_STATE, "the planar mode cannot change while a tape is recorded");
-  s->planar_on = enable != 0;
+  if (s->tape && (enable != 0) != s->reduced_on)
+    return fail(s, MAXENT_E_STATE, "the reduced-kernel mode cannot change while a tape is recorded");
+  s->reduced_on = enable != 0;
   return MAXENT_OK;
 }
 
@@ -1084,11 +1089,11 @@ static hipError_t batch_enqueue(maxent_solver* s, int steps, hipStream_t st) {
     if (e != hipSuccess) return e;
     p.Ub = s->U; p.Ua = s->U; p.Uout = s->Us;
     p.mode = mx::MODE_EULER; p.cdt = mid ? 0.5 : 1.0; p.do_cfl = 0;
-    e = mx::launch_batch_stage(prec, b->nt, b->cpt, p, grid, st);
+    e = mx::launch_batch_stage(prec, s->reduced(), b->nt, b->cpt, p, grid, st);
     if (e != hipSuccess) return e;
     p.Ub = s->Us; p.Ua = s->U; p.Uout = s->U;
     p.mode = mid ? mx::MODE_MID2 : mx::MODE_HEUN2; p.cdt = 1.0; p.do_cfl = 1;
-    e = mx::launch_batch_stage(prec, b->nt, b->cpt, p, grid, st);
+    e = mx::launch_batch_stage(prec, s->reduced(), b->nt, b->cpt, p, grid, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -13,6 +13,7 @@
 #include "mx_internal.hpp"
 #include "mx_physics.hpp"
 #include "mx_scheme.hpp"
+#include "mx_axial.hpp"
 #include "mx_batch.hpp"
 
 namespace mx {
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(1024) void batch_finalize_kernel(BatchInst* in, con
 // finds its first tile by a binary search over the tile prefix and then walks forward.
 // Two waves per SIMD: the register budget is 256 per lane.
 template <class SYS, int ORDER, int PREC, int NT, int CPT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SYS::NV <= 7 ? 3 : 2)))
 void batch_stage_kernel(BatchParams p) {
   constexpr int NV = SYS::NV;
   constexpr int TX = tile_1d(CPT * NT);
@@ -194,7 +195,7 @@ void batch_stage_kernel(BatchParams p) {
       int si = bmap(i0 + cc - G, n, p.bc_lo, p.bc_hi, rx);
       double Uc[NV], W[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Uc[v] = p.Ub[v * p.plane + off + si];
+      for (int v = 0; v < NV; ++v) Uc[v] = p.Ub[SYS::plane_of(v) * p.plane + off + si];
       SYS::cons_to_prim(Uc, W);
       if (rx) {
 #pragma unroll
@@ -257,7 +258,7 @@ void batch_stage_kernel(BatchParams p) {
       long long g = off + i0 + ci;
       double Ub[NV], W[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[v * p.plane + g];
+      for (int v = 0; v < NV; ++v) Ub[v] = p.Ub[SYS::plane_of(v) * p.plane + g];
       SYS::cons_to_prim(Ub, W);
       double Cs[NV];
       const double tau_ref = c->tau_ref;
@@ -277,10 +278,10 @@ void batch_stage_kernel(BatchParams p) {
         L = L + Cs[v];
         double o;
         if (p.mode == MODE_EULER) o = Ub[v] + (p.cdt * dt) * L;
-        else if (p.mode == MODE_HEUN2) o = 0.5 * p.Ua[v * p.plane + g] + 0.5 * (Ub[v] + dt * L);
-        else o = p.Ua[v * p.plane + g] + dt * L;
+        else if (p.mode == MODE_HEUN2) o = 0.5 * p.Ua[SYS::plane_of(v) * p.plane + g] + 0.5 * (Ub[v] + dt * L);
+        else o = p.Ua[SYS::plane_of(v) * p.plane + g] + dt * L;
         Un[v] = o;
-        p.Uout[v * p.plane + g] = o;
+        p.Uout[SYS::plane_of(v) * p.plane + g] = o;
       }
       bool fin = true;
 #pragma unroll
@@ -345,20 +346,20 @@ __global__ __launch_bounds__(256) void batch_cfl_kernel(BatchParams p, long long
   }
 }
 
-template <int PREC, int NT, int CPT>
+template <class SYS, int PREC, int NT, int CPT>
 static hipError_t launch_bs(const BatchParams& p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((batch_stage_kernel<Sys14, 2, PREC, NT, CPT>), dim3(grid), dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((batch_stage_kernel<SYS, 2, PREC, NT, CPT>), dim3(grid), dim3(NT), 0, s, p);
   return hipGetLastError();
 }
 
-template <int PREC>
+template <class SYS, int PREC>
 static hipError_t launch_bs_p(int nt, int cpt, const BatchParams& p, int grid, hipStream_t s) {
-  if (nt == 64 && cpt == 1) return launch_bs<PREC, 64, 1>(p, grid, s);
-  if (nt == 64 && cpt == 2) return launch_bs<PREC, 64, 2>(p, grid, s);
-  if (nt == 64 && cpt == 4) return launch_bs<PREC, 64, 4>(p, grid, s);
-  if (nt == 128 && cpt == 1) return launch_bs<PREC, 128, 1>(p, grid, s);
-  if (nt == 128 && cpt == 2) return launch_bs<PREC, 128, 2>(p, grid, s);
-  if (nt == 256 && cpt == 1) return launch_bs<PREC, 256, 1>(p, grid, s);
+  if (nt == 64 && cpt == 1) return launch_bs<SYS, PREC, 64, 1>(p, grid, s);
+  if (nt == 64 && cpt == 2) return launch_bs<SYS, PREC, 64, 2>(p, grid, s);
+  if (nt == 64 && cpt == 4) return launch_bs<SYS, PREC, 64, 4>(p, grid, s);
+  if (nt == 128 && cpt == 1) return launch_bs<SYS, PREC, 128, 1>(p, grid, s);
+  if (nt == 128 && cpt == 2) return launch_bs<SYS, PREC, 128, 2>(p, grid, s);
+  if (nt == 256 && cpt == 1) return launch_bs<SYS, PREC, 256, 1>(p, grid, s);
   return hipErrorInvalidValue;
 }
 
@@ -367,8 +368,11 @@ bool batch_shape_supported(int nt, int cpt) {
          (nt == 256 && cpt == 1);
 }
 
-hipError_t launch_batch_stage(int precision, int nt, int cpt, const BatchParams& p, int grid, hipStream_t s) {
-  return precision == 0 ? launch_bs_p<0>(nt, cpt, p, grid, s) : launch_bs_p<1>(nt, cpt, p, grid, s);
+hipError_t launch_batch_stage(int precision, bool reduced, int nt, int cpt, const BatchParams& p, int grid,
+                              hipStream_t s) {
+  if (reduced)
+    return precision == 0 ? launch_bs_p<Sys14A, 0>(nt, cpt, p, grid, s) : launch_bs_p<Sys14A, 1>(nt, cpt, p, grid, s);
+  return precision == 0 ? launch_bs_p<Sys14, 0>(nt, cpt, p, grid, s) : launch_bs_p<Sys14, 1>(nt, cpt, p, grid, s);
 }
 
 hipError_t launch_batch_finalize(BatchInst* in, const int* order, int n_inst, double cfl, int tile_w,

@@ -47,7 +47,10 @@ struct BatchParams {
 
 // launch shapes: nt threads per workgroup, cpt cells per thread (tiles of tile_1d(nt * cpt))
 bool batch_shape_supported(int nt, int cpt);
-hipError_t launch_batch_stage(int precision, int nt, int cpt, const BatchParams& p, int grid, hipStream_t s);
+// reduced: every tube's state is axially symmetric (u_y = u_z = P_xy = P_xz = P_yz = q_y = q_z = 0)
+// and the stages carry the seven other moments (Sys14A)
+hipError_t launch_batch_stage(int precision, bool reduced, int nt, int cpt, const BatchParams& p, int grid,
+                              hipStream_t s);
 hipError_t launch_batch_finalize(BatchInst* in, const int* order, int n_inst, double cfl, int tile_w,
                                  int* act_inst, int* act_tile0, BatchCtrl* bc, int stage_grid,
                                  hipStream_t s);

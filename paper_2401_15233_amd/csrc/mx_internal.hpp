@@ -20,8 +20,11 @@ struct DevCtrl {
   long long n_fp64;              // mixed precision: face states re-evaluated in FP64
   long long n_states;            // mixed precision: face states evaluated
   long long n_sigma_limited;     // cells with sigma < sigma_lim (set by the counting kernel)
-  int nonplanar;                 // set by the ingest kernel: a z-odd moment is non-zero
+  int asym;                      // set by the ingest kernel: bit 1 a z-odd moment (u_z, P_xz,
+                                 // P_yz, q_z) is non-zero somewhere, bit 2 a y-odd one (u_y,
+                                 // P_xy, P_yz, q_y)
 };
+enum { ASYM_Z = 1, ASYM_Y = 2 };
 
 // 1D tiles: a workgroup of NT threads owns NT - 4 cells, so that the cells plus the two-cell
 // halo on each side (NT), the limiter items (NT - 2) and the faces (NT - 3) each take a single
@@ -67,16 +70,18 @@ struct CflParams {
 };
 
 // launchers (mx_kernels.hip)
-// planar (2D, 14 moments): the state is planar-symmetric (u_z = P_xz = P_yz = q_z = 0) and
-// the stage runs on the ten other moments (Sys14P)
-hipError_t launch_stage(int system, int dim, int order, int precision, bool planar,
+// reduced (14 moments): the state is symmetric and the stage carries only the moments that can
+// be non-zero -- 2D planar (u_z = P_xz = P_yz = q_z = 0; ten moments, Sys14P), 1D axial (also
+// u_y = P_xy = q_y = 0; seven moments, Sys14A)
+hipError_t launch_stage(int system, int dim, int order, int precision, bool reduced,
                         const StageParams& p, hipStream_t s);
 hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s);
 hipError_t launch_finalize(DevCtrl* c, int dim, double cfl, double dx, hipStream_t s);
 hipError_t launch_ctrl_set(DevCtrl* c, double dt_fixed, double t_end, hipStream_t s);
 hipError_t launch_ctrl_reset(DevCtrl* c, double t0, hipStream_t s);
-// zero the z-odd planes (3, 6, 8, 12) of a 14-moment field of `plane` doubles per plane (a
-// kernel, no memset); nothing for nv != 14
+// zero the planes a reduced kernel never writes (2, 3, 5, 6, 8, 11, 12: u_y, u_z, P_xy, P_xz,
+// P_yz, q_y, q_z) of a 14-moment field of `plane` doubles per plane (a kernel, no memset);
+// nothing for nv != 14
 hipError_t launch_zero_planes(double* U, long long plane, int nv, hipStream_t s);
 // src/dst: unpadded [nv][ny][nx]; U: padded [nv][ny][pitch]
 hipError_t launch_ingest(int system, int repr, const double* src, double* U, int nx, int ny,

@@ -20,6 +20,7 @@
 #include "mx_scheme.hpp"
 #include "mx_bc.hpp"
 #include "mx_planar.hpp"
+#include "mx_axial.hpp"
 
 namespace mx {
 
@@ -426,17 +427,18 @@ __global__ void ctrl_reset_kernel(DevCtrl* c, double t0) {
   if (threadIdx.x == 0) {
     c->dt = 0.0; c->t = t0; c->t_end = 0.0; c->dt_fixed = 0.0; c->dt_last = 0.0;
     c->maxrate = 0ull; c->step = 0; c->n_fallback = 0; c->status = 0; c->fail_step = 0x7fffffff;
-    c->n_fp64 = 0; c->n_states = 0; c->n_sigma_limited = 0; c->nonplanar = 0;
+    c->n_fp64 = 0; c->n_states = 0; c->n_sigma_limited = 0; c->asym = 0;
   }
 }
 
-// zero the z-odd planes (u_z, P_xz, P_yz, q_z) of a 14-moment field
+// zero the planes no reduced kernel writes (u_y, u_z, P_xy, P_xz, P_yz, q_y, q_z) of a
+// 14-moment field
 __global__ __launch_bounds__(256) void zero_planes_kernel(double* U, long long plane) {
-  const long long n = 4 * plane;
+  const long long n = 7 * plane;
   for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
     const int w = (int)(k / plane);
     const long long o = k - w * plane;
-    const int v = w == 0 ? 3 : (w == 1 ? 6 : (w == 2 ? 8 : 12));
+    const int v = w == 0 ? 2 : (w == 1 ? 3 : (w == 2 ? 5 : (w == 3 ? 6 : (w == 4 ? 8 : (w == 5 ? 11 : 12)))));
     U[v * plane + o] = 0.0;
   }
 }
@@ -472,15 +474,18 @@ __global__ void ingest_kernel(int repr, const double* src, double* U, int nx, in
     }
     if (!fin) bad |= ST_NONFINITE;
     else if (!SYS::admissible(W)) bad |= ST_UNREALIZABLE;
-    // planar symmetry (14 moments): u_z, P_xz, P_yz and q_z all exactly zero
-    if constexpr (NV == 14)
-      if (Uc[3] != 0.0 || Uc[6] != 0.0 || Uc[8] != 0.0 || Uc[12] != 0.0) np = 1;
+    // symmetry (14 moments): z-odd moments u_z, P_xz, P_yz, q_z and y-odd moments u_y, P_xy,
+    // P_yz, q_y exactly zero
+    if constexpr (NV == 14) {
+      if (Uc[3] != 0.0 || Uc[6] != 0.0 || Uc[8] != 0.0 || Uc[12] != 0.0) np |= ASYM_Z;
+      if (Uc[2] != 0.0 || Uc[5] != 0.0 || Uc[8] != 0.0 || Uc[11] != 0.0) np |= ASYM_Y;
+    }
   }
   bad = wave_or(bad);
   if ((threadIdx.x & 63) == 0 && bad) atomicOr(&c->status, bad);
   if constexpr (NV == 14) {
     np = wave_or(np);
-    if ((threadIdx.x & 63) == 0 && np) atomicOr(&c->nonplanar, 1);
+    if ((threadIdx.x & 63) == 0 && np) atomicOr(&c->asym, np);
   }
 }
 
@@ -579,24 +584,27 @@ static hipError_t launch_stage_t(const StageParams& p, hipStream_t s) {
 }
 
 template <int PREC>
-static hipError_t launch_stage_p(int system, int dim, int order, bool planar, const StageParams& p,
+static hipError_t launch_stage_p(int system, int dim, int order, bool reduced, const StageParams& p,
                                  hipStream_t s) {
   if (system == 5) {
     if (dim != 1) return hipErrorInvalidValue;
     return order == 2 ? launch_stage_t<Sys5, 1, 2, PREC>(p, s) : launch_stage_t<Sys5, 1, 1, PREC>(p, s);
   }
-  if (dim == 1)
+  if (dim == 1) {
+    if (reduced)
+      return order == 2 ? launch_stage_t<Sys14A, 1, 2, PREC>(p, s) : launch_stage_t<Sys14A, 1, 1, PREC>(p, s);
     return order == 2 ? launch_stage_t<Sys14, 1, 2, PREC>(p, s) : launch_stage_t<Sys14, 1, 1, PREC>(p, s);
-  if (planar)
+  }
+  if (reduced)
     return order == 2 ? launch_stage_t<Sys14P, 2, 2, PREC>(p, s) : launch_stage_t<Sys14P, 2, 1, PREC>(p, s);
   return order == 2 ? launch_stage_t<Sys14, 2, 2, PREC>(p, s) : launch_stage_t<Sys14, 2, 1, PREC>(p, s);
 }
 
-hipError_t launch_stage(int system, int dim, int order, int precision, bool planar,
+hipError_t launch_stage(int system, int dim, int order, int precision, bool reduced,
                         const StageParams& p, hipStream_t s) {
-  if (precision == 1) return launch_stage_p<1>(system, dim, order, planar, p, s);
-  if (precision == 2) return launch_stage_p<2>(system, dim, order, planar, p, s);
-  return launch_stage_p<0>(system, dim, order, planar, p, s);
+  if (precision == 1) return launch_stage_p<1>(system, dim, order, reduced, p, s);
+  if (precision == 2) return launch_stage_p<2>(system, dim, order, reduced, p, s);
+  return launch_stage_p<0>(system, dim, order, reduced, p, s);
 }
 
 hipError_t launch_cfl(int system, int dim, const CflParams& p, hipStream_t s) {
@@ -626,7 +634,7 @@ hipError_t launch_ctrl_reset(DevCtrl* c, double t0, hipStream_t s) {
 
 hipError_t launch_zero_planes(double* U, long long plane, int nv, hipStream_t s) {
   if (nv != 14) return hipSuccess;
-  long long n = 4 * plane;
+  long long n = 7 * plane;
   int grid = (int)((n + 255) / 256);
   if (grid > 8192) grid = 8192;
   hipLaunchKernelGGL(zero_planes_kernel, dim3(grid), dim3(256), 0, s, U, plane);

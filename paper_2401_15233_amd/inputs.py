@@ -205,6 +205,50 @@ def random_planar_states14(n, seed=0):
     return W
 
 
+def random_axial_states14(n, seed=0):
+    """n realizable 14-moment states of a 1D flow along x whose distribution is even in v_y
+    and in v_z (u_y = u_z = P_xy = P_xz = P_yz = q_y = q_z = 0 exactly): Maxwellians moving
+    along x, 2- and 3-beam mixtures with means on the x axis, particle sets mirrored in v_y
+    and in v_z (so P_yy and P_zz differ), with random density, velocity scale and x-boost."""
+    rng = np.random.default_rng(seed)
+    fam = rng.integers(0, 4, size=n)
+    W = np.empty((14, n))
+    i0 = np.nonzero(fam == 0)[0]
+    W[:, i0] = _maxw14(np.ones(len(i0)), 0.0, 0.0, 0.0, np.ones(len(i0)))
+    for f, K in ((1, 2), (2, 3)):
+        ii = np.nonzero(fam == f)[0]
+        if len(ii):
+            w = rng.uniform(0.05, 1.0, size=(K, len(ii)))
+            m = rng.normal(0.0, 1.5, size=(K, 3, len(ii)))
+            m[:, 1:] = 0.0
+            T = rng.uniform(0.05, 1.5, size=(K, len(ii)))
+            W[:, ii] = beam_mixture14(w, m, T)
+    ii = np.nonzero(fam == 3)[0]
+    if len(ii):
+        M = 3
+        w = rng.uniform(0.1, 1.0, size=(M, len(ii)))
+        v = rng.normal(0.0, 1.0, size=(M, 3, len(ii)))
+        vs, ws = [], []
+        for sy in (1.0, -1.0):
+            for sz in (1.0, -1.0):
+                vm = v.copy()
+                vm[:, 1] *= sy
+                vm[:, 2] *= sz
+                vs.append(vm)
+                ws.append(w)
+        W[:, ii] = particle_moments14(np.concatenate(ws), np.concatenate(vs))
+    # the y- and z-odd moments vanish by symmetry; drop the sums' rounding residue
+    W[[2, 3, 5, 6, 8, 11, 12]] = 0.0
+    a = np.exp(rng.uniform(math.log(1e-3), math.log(10.0), size=n))
+    b = np.exp(rng.uniform(math.log(0.3), math.log(3.0), size=n))
+    W[0] *= a
+    W[1] = W[1] * b + rng.normal(0.0, 2.0, size=n)
+    W[4:10] *= a * b**2
+    W[10:13] *= a * b**3
+    W[13] *= a * b**4
+    return W
+
+
 def random_states5(n, seed=0):
     rng = np.random.default_rng(seed)
     fam = rng.integers(0, 4, size=n)

@@ -32,7 +32,7 @@ EXPORTED = ('maxent_create', 'maxent_init_state', 'maxent_step', 'maxent_get_mom
             'maxent_create_batch', 'maxent_step_batch', 'maxent_set_batch_launch',
             'maxent_get_batch_launch', 'maxent_autotune_batch', 'maxent_record',
             'maxent_set_inflow', 'maxent_step_adjoint', 'maxent_tape_info',
-            'maxent_set_adjoint_mode', 'maxent_step_noalloc', 'maxent_set_planar')
+            'maxent_set_adjoint_mode', 'maxent_step_noalloc', 'maxent_set_reduced')
 
 
 class MaxentError(RuntimeError):
@@ -67,7 +67,7 @@ class Info(ctypes.Structure):
                 ('fail_step', ctypes.c_int), ('fail_code', ctypes.c_int),
                 ('n_fp64_states', ctypes.c_longlong), ('n_face_states', ctypes.c_longlong),
                 ('n_sigma_limited', ctypes.c_longlong), ('fp64_fraction', ctypes.c_double),
-                ('planar', ctypes.c_int), ('reserved', ctypes.c_int)]
+                ('reduced', ctypes.c_int), ('reserved', ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -137,7 +137,7 @@ def load_library(path=LIB_PATH):
     L.maxent_set_inflow.argtypes = [vp, ctypes.c_double, ctypes.c_double]
     L.maxent_tape_info.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), vp]
     L.maxent_set_adjoint_mode.argtypes = [vp, ctypes.c_int]
-    L.maxent_set_planar.argtypes = [vp, ctypes.c_int]
+    L.maxent_set_reduced.argtypes = [vp, ctypes.c_int]
     L.maxent_step_adjoint.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_double)]
     L.maxent_step_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Numerics), vp,
@@ -313,10 +313,10 @@ class MaxEntSolver:
         """'exact' (default) or 'frozen_limiter'."""
         self._check(self._lib.maxent_set_adjoint_mode(self._h, ADJOINT_MODE[mode]))
 
-    def set_planar(self, enable):
-        """Planar-symmetric 2D 14-moment states run the planar stage kernel (True, the
-        default) or always the full 14-moment kernel (False)."""
-        self._check(self._lib.maxent_set_planar(self._h, 1 if enable else 0))
+    def set_reduced(self, enable):
+        """Symmetric 14-moment states (2D planar, 1D axial) run the reduced stage kernels
+        (True, the default) or always the full 14-moment kernels (False)."""
+        self._check(self._lib.maxent_set_reduced(self._h, 1 if enable else 0))
 
     def tape(self):
         """Time steps of the recorded steps (NumPy array)."""

@@ -46,7 +46,7 @@ def test_struct_layouts_match_header():
     assert S.Numerics.source_implicit.offset == 52
     assert ctypes.sizeof(S.Info) == 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 4 + 4
     assert S.Info.n_sigma_limited.offset == 56 and S.Info.fp64_fraction.offset == 64
-    assert S.Info.planar.offset == 72
+    assert S.Info.reduced.offset == 72
 
 
 def test_struct_layout_matches_the_c_compiler(tmp_path):

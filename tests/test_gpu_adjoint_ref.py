@@ -121,14 +121,14 @@ def test_planar_adjoint_equals_full_adjoint(gpu_lib):
 
     def run(w, planar, mode):
         s = gpu_lib.MaxEntSolver(**kw)
-        s.set_planar(planar)
+        s.set_reduced(planar)
         s.set_adjoint_mode(mode)
         s.init_state(np.ascontiguousarray(U0), repr='conserved')
         s.record(10, 40)
         info = s.step(40, tau_ref=TAU_JET)
         gU0, g = s.adjoint(w)
         s.close()
-        return info['planar'], np.asarray(g), gU0.cpu().numpy()
+        return info['reduced'], np.asarray(g), gU0.cpu().numpy()
 
     for label, w in (('strip', strip_weights(n, n, 0.05, 0.15, 0.5, 1.0, 1 / n, 1 / n)),
                      ('random', random_weights(n, n, 1 / n, 1 / n, seed=5))):

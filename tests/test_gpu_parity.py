@@ -35,9 +35,9 @@ TAU_SOD = I.kn_to_tau_ref(0.01)
 TAU_JET = I.kn_to_tau_ref(0.1, L_ref=0.1)
 
 
-def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, planar=True):
+def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, reduced=True):
     s = S.MaxEntSolver(**kw)
-    s.set_planar(planar)
+    s.set_reduced(reduced)
     s.init_state(np.ascontiguousarray(W0))
     info = s.step(n, dt=dt, tau_ref=tau_ref, t_end=t_end, check=check)
     U = s.get('conserved').cpu().numpy()
@@ -45,9 +45,9 @@ def gpu_run(S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, planar=Tru
     return U, info
 
 
-def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, trials=3, planar=True):
+def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, trials=3, reduced=True):
     """Run both sides, print the errors, assert the condition-aware bar."""
-    Ug, info = gpu_run(S, kw, W0, n if n is not None else 20000, dt, tau_ref, t_end, check, planar)
+    Ug, info = gpu_run(S, kw, W0, n if n is not None else 20000, dt, tau_ref, t_end, check, reduced)
     base, spread, t, nst, (s_in, s_mid) = ob.oracle_with_spread(
         kw, W0, nsteps=n, dt=dt, tau_ref=tau_ref, t_end=t_end, trials=trials, check=check,
         parts=True)
@@ -59,7 +59,7 @@ def compare(name, S, kw, W0, n, dt=0.0, tau_ref=0.0, t_end=0.0, check=True, tria
 
     print(f'{name}: field-relative error max {err.max():.2e}, oracle spread max: input '
           f'{rel(s_in):.2e}, intermediate {rel(s_mid):.2e}; bound use {ratio:.2f}; '
-          f'steps gpu {info["steps"]} oracle {nst}; planar kernel {info["planar"]}', flush=True)
+          f'steps gpu {info["steps"]} oracle {nst}; reduced kernel {info["reduced"]}', flush=True)
     print(f'   per moment {np.array2string(err, precision=1)}', flush=True)
     assert ok, (f'{name}: error exceeds 1e-12 + {ob.SPREAD_FACTOR:g} x oracle spread '
                 f'(ratio {ratio:.2f})')
@@ -104,10 +104,16 @@ def test_sod14_muscl_rk2_one_step(gpu_lib, nx):
             tau_ref=TAU_SOD)
 
 
-def test_sod14_muscl_rk2_many_steps(gpu_lib):
-    Ug, info, base, t, n = compare('sod14 60 steps', gpu_lib, SOD14, I.sod_prims(14, 200), 60,
-                                   tau_ref=TAU_SOD)
+@pytest.mark.parametrize('reduced', [True, False])
+def test_sod14_muscl_rk2_many_steps(gpu_lib, reduced):
+    """The tube of Maxwellians at rest is axially symmetric: the axial kernel (seven moments)
+    by default, the full 14-moment kernel with the reduced mode off; both against the oracle."""
+    Ug, info, base, t, n = compare(f'sod14 60 steps reduced={reduced}', gpu_lib, SOD14,
+                                   I.sod_prims(14, 200), 60, tau_ref=TAU_SOD, reduced=reduced)
     assert abs(info['t'] - t) < 1e-12 * t
+    assert info['reduced'] == (2 if reduced else 0)
+    if reduced:
+        assert np.all(Ug[[2, 3, 5, 6, 8, 11, 12]] == 0.0)
 
 
 @pytest.mark.parametrize('kn', [1e-3, 1e-2, 0.1, 1.0, 10.0])
@@ -169,9 +175,9 @@ def test_jets_2d_developed_field(gpu_lib, planar):
     W0 = I.crossed_jets_developed(nx, ny, seed=2)
     for n_steps in (1, 4):
         Ug, info, base, t, n = compare(f'jets 70x50 {n_steps} steps', gpu_lib, kw, W0, n_steps,
-                                       tau_ref=TAU_JET, planar=planar)
+                                       tau_ref=TAU_JET, reduced=planar)
         assert abs(info['t'] - t) < 1e-12 * t
-        assert info['planar'] == int(planar)
+        assert info['reduced'] == int(planar)
         if planar:
             assert np.all(Ug[[3, 6, 8, 12]] == 0.0)
 
@@ -208,7 +214,7 @@ def test_2d_periodic_reflective_smooth(gpu_lib, planar):
     Ug, info, _, _, _ = compare(f'2d periodic/reflective planar={planar}', gpu_lib, kw,
                                 I.random_smooth_field14(nx, ny, seed=8, planar=planar), 3,
                                 tau_ref=0.03)
-    assert info['planar'] == int(planar)
+    assert info['reduced'] == int(planar)
 
 
 # ------------------------------------------------------------------ full size
@@ -279,7 +285,7 @@ def test_full_size_periodic_conservation(gpu_lib, planar):
     W0 = I.random_smooth_field14(n, n, seed=12, planar=planar)
     U0 = mo.prim_to_cons14(W0)
     Ug, info = gpu_run(gpu_lib, kw, W0, 3, tau_ref=0.02)
-    assert info['planar'] == int(planar)
+    assert info['reduced'] == int(planar)
     for comp in ([0], [1], [2], [3], [4, 7, 9]):
         a = U0[comp].sum()
         b = Ug[comp].sum()
@@ -374,10 +380,15 @@ def test_planar_detection(gpu_lib):
         if v is not None:
             W[v, 17, 23] = 1e-9 * (1.0 if v != 6 and v != 8 else W[4, 17, 23])
         _, info = gpu_run(gpu_lib, kw, W, 1, tau_ref=TAU_JET)
-        assert info['planar'] == expect, v
-    # 1D and 5-moment solvers never use it
-    _, info = gpu_run(gpu_lib, SOD14, I.sod_prims(14, 200), 1, tau_ref=TAU_SOD)
-    assert info['planar'] == 0
+        assert info['reduced'] == expect, v
+    # a 1D tube of Maxwellians at rest is axially symmetric: the axial kernel; a y-odd moment
+    # (u_y here) selects the full one
+    W = I.sod_prims(14, 200)
+    _, info = gpu_run(gpu_lib, SOD14, W, 1, tau_ref=TAU_SOD)
+    assert info['reduced'] == 2
+    W[2, 77] = 1e-9
+    _, info = gpu_run(gpu_lib, SOD14, W, 1, tau_ref=TAU_SOD)
+    assert info['reduced'] == 0
 
 
 def test_planar_pingpong_after_a_nonplanar_state(gpu_lib):
@@ -391,11 +402,11 @@ def test_planar_pingpong_after_a_nonplanar_state(gpu_lib):
     try:
         s.init_state(I.random_smooth_field14(nx, ny, seed=4))
         info = s.step(3, tau_ref=0.05)
-        assert info['planar'] == 0
+        assert info['reduced'] == 0
         Wp = I.random_smooth_field14(nx, ny, seed=5, planar=True)
         s.init_state(Wp)
         info = s.step(3, tau_ref=0.05)
-        assert info['planar'] == 1
+        assert info['reduced'] == 1
         U1 = s.get('conserved').cpu().numpy()
     finally:
         s.close()
@@ -411,7 +422,7 @@ def test_planar_mode_is_fixed_while_a_tape_is_recorded(gpu_lib):
         s.init_state(I.crossed_jets_initial(nx, ny))
         s.record(2, 8)
         with pytest.raises(gpu_lib.MaxentError):
-            s.set_planar(False)
-        s.set_planar(True)          # unchanged: allowed
+            s.set_reduced(False)
+        s.set_reduced(True)         # unchanged: allowed
     finally:
         s.close()

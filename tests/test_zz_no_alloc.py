@@ -55,7 +55,7 @@ def check_same(S, kw, U0, n, **k):
     Uh, ih = handle(S, kw, U0, n, **k)
     assert rc == 0, S.load_library().maxent_last_error(None)
     assert info['steps'] == ih['steps'] and info['t'] == ih['t'] and info['dt_last'] == ih['dt_last']
-    assert info['planar'] == ih['planar']
+    assert info['reduced'] == ih['reduced']
     assert np.array_equal(Un, Uh)
     return info
 
@@ -85,10 +85,10 @@ def test_planar_forward_euler_after_a_nonplanar_call(gpu_lib):
     kw = dict(JETS, nx=48, ny=40, integrator='fe', limiter='vanalbada', bc=('periodic',) * 4, jets=[])
     i1 = check_same(gpu_lib, kw, mo.prim_to_cons14(I.random_smooth_field14(48, 40, seed=4)), 3,
                     tau_ref=0.05)
-    assert i1['planar'] == 0
+    assert i1['reduced'] == 0
     Up = mo.prim_to_cons14(I.random_smooth_field14(48, 40, seed=5, planar=True))
     i2 = check_same(gpu_lib, kw, Up, 3, tau_ref=0.05)
-    assert i2['planar'] == 1
+    assert i2['reduced'] == 1
     rc, Un, _ = noalloc(gpu_lib, kw, Up, 3, tau_ref=0.05)
     assert rc == 0 and np.all(Un[[3, 6, 8, 12]] == 0.0)
 
