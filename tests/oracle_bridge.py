@@ -257,18 +257,19 @@ def oracle_with_l1_spread(kw, W0, t_end, tau_ref, trials=3, seed=0, perturb=PERT
 
 
 def oracle_with_flux_rounding_spread(kw, W0, tau_ref, nsteps, trials=2, seed=0, rel=2.0 ** -24):
-    """The oracle's L1 change per moment when every physical flux component and every wave
-    speed it evaluates carries one random relative rounding of size rel (2^-24: one FP32
-    rounding), with the oracle's arithmetic otherwise untouched: how far a correct
-    computation whose fluxes are rounded to single precision at each evaluation can move.
-    Returns (base, spread)."""
+    """The oracle's L1 change per moment when every closure (closing moments), physical flux
+    component and wave speed it evaluates carries one random relative rounding of size rel
+    (2^-24: one FP32 rounding), with the oracle's arithmetic otherwise untouched: how far a
+    correct computation whose per-face closure, flux and wave-speed evaluations are rounded to
+    single precision can move.  Returns (base, spread)."""
     s = to_setup(kw)
     U0 = prim_to_cons(np.asarray(W0, dtype=float), s.system)
     if s.dim == 1:
         U0 = U0.reshape(U0.shape[0], -1)
     base, _, _ = sc.run(U0, s, tau_ref, nsteps=nsteps)
     rng = np.random.default_rng(seed)
-    names = ('flux14', 'wavespeeds14') if s.system == 14 else ('flux5', 'wavespeeds5')
+    names = (('flux14', 'wavespeeds14', 'closure14') if s.system == 14
+             else ('flux5', 'wavespeeds5', 'closure5'))
     orig = {k: getattr(sc, k) for k in names}
 
     def rnd(a):
@@ -282,10 +283,16 @@ def oracle_with_flux_rounding_spread(kw, W0, tau_ref, nsteps, trials=2, seed=0, 
         lmin, lmax = orig[names[1]](*a, **k)
         return rnd(lmin), rnd(lmax)
 
+    def closure(*a, **k):
+        out = orig[names[2]](*a, **k)
+        # the closing values; the last item (sigma) is not a flux input
+        return tuple(rnd(x) for x in out[:-1]) + (out[-1],)
+
     spread = np.zeros(base.shape[0])
     try:
         setattr(sc, names[0], flux)
         setattr(sc, names[1], speeds)
+        setattr(sc, names[2], closure)
         for _ in range(trials):
             out, _, _ = sc.run(U0, s, tau_ref, nsteps=nsteps)
             spread = np.maximum(spread, np.abs(out - base).reshape(base.shape[0], -1).sum(1))
