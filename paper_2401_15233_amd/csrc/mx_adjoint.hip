@@ -80,6 +80,15 @@ __device__ __forceinline__ double ld(const double* f, int v, long long stride, l
   return (PL && zodd(v)) ? 0.0 : f[v * stride + k];
 }
 
+// launders the forward closure core before the reverse (opaque, mx_adjoint.hpp)
+template <class K> __device__ __forceinline__ void opaque_core(K& k) {
+  opaque(k.rho); opaque(k.c); opaque(k.t1); opaque(k.t2); opaque(k.A); opaque(k.sig); opaque(k.sb);
+#pragma unroll
+  for (int m = 0; m < 6; ++m) { opaque(k.Ph[m]); opaque(k.P2[m]); }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { opaque(k.qh[i]); opaque(k.z[i]); }
+}
+
 template <bool PL>
 __device__ __forceinline__ void get_w(const AdjParams& a, long long e, double* W) {
 #pragma unroll
@@ -141,7 +150,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
 
 // ------------------------------------------------------------------ 1. faces
 template <int D, int DIM, int ORDER, bool PL>
-__global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
+__global__ __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(PL ? 2 : 1))) void adj_face_kernel(AdjParams a) {
   // lanes 2k and 2k+1 own the left and the right state of face k; the grid has two threads
   // per face, so both lanes of a pair pass or fail every face-uniform test together
   const StageParams& p = a.sp;
@@ -224,7 +233,17 @@ __global__ __launch_bounds__(ADJ_NT) void adj_face_kernel(AdjParams a) {
   double Wb[14];
 #pragma unroll
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
-  if (any2) Adj14::face_terms_vjp_prepared<D>(k, Qd, Rd, Sd, W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
+  if (any2) {
+#pragma unroll
+    for (int v = 0; v < 14; ++v) opaque(W[v]);
+    opaque_core(k);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) opaque(Qd[m]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) opaque(Rd[i]);
+    opaque(Sd);
+    Adj14::face_terms_vjp_prepared<D>(k, Qd, Rd, Sd, W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
+  }
 #pragma unroll
   for (int v = 0; v < 14; ++v)
     if (!(PL && zodd(v))) out[v * nf] = Wb[v];

@@ -16,6 +16,19 @@
 
 namespace mx {
 
+// Hides a value's origin from the device compiler; no instruction is emitted and host code
+// is unchanged.  A reverse that reads the laundered copy recomputes the forward intermediates
+// it needs where it needs them, instead of the compiler sharing them with an earlier forward
+// evaluation (or hoisting them) and keeping them live across the whole reverse.  Compile-time
+// constants (the z-odd zeros of a planar run) are left as they are, so that they still fold.
+template <class T> MX_HD inline void opaque(T& x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (!__builtin_constant_p(x)) asm volatile("" : "+v"(x));
+#else
+  (void)x;
+#endif
+}
+
 // symmetric (stored) y = S x: reverse
 template <class T> MX_HD void symv_vjp(const T* S, const T* x, const T* yb, T* Sb, T* xb) {
 #pragma unroll
@@ -527,25 +540,29 @@ struct Adj14 {
 
   // hyperbola(zeta, rest) reverse
   template <class T> MX_HD static void hyperbola_vjp(T zeta, T rest, T hb, T& zetab, T& restb) {
+    // the partials are formed in locals and added once at the end (no branch writes through
+    // the references, which keeps both callers' accumulators in registers)
     T X = zeta * zeta + rest;
-    if (!(X > T(0))) { zetab += hb; return; }
-    T sX = msqrt(X);
-    T Xb = T(0);
-    if (zeta >= T(0)) {
-      zetab += hb;
-      T sXb = hb;
-      sqrt_vjp(X, sX, sXb, Xb);
-    } else {
-      T den = sX - zeta;
-      T h = mdiv(rest, den);
-      T iden = mrcp(den);
-      restb += hb * iden;
-      T denb = -hb * h * iden;
-      sqrt_vjp(X, sX, denb, Xb);
-      zetab -= denb;
+    T zb = hb, rb = T(0);
+    if (X > T(0)) {
+      T sX = msqrt(X);
+      T Xb = T(0);
+      if (zeta >= T(0)) {
+        sqrt_vjp(X, sX, hb, Xb);
+      } else {
+        T den = sX - zeta;
+        T h = mdiv(rest, den);
+        T iden = mrcp(den);
+        rb = hb * iden;
+        T denb = -hb * h * iden;
+        sqrt_vjp(X, sX, denb, Xb);
+        zb = -denb;
+      }
+      zb += T(2) * zeta * Xb;
+      rb += Xb;
     }
-    zetab += T(2) * zeta * Xb;
-    restb += Xb;
+    zetab += zb;
+    restb += rb;
   }
 
   // wavespeeds<d>(k, ud) -> (lmin, lmax): kb, udb
@@ -699,7 +716,21 @@ struct Adj14 {
     zero(kb);
     wavespeeds_vjp<d>(k, W[1 + d], kws, lminb, lmaxb, kb, Wb[1 + d]);
     closure_dir_vjp<d>(k, Qdb, Rdb, Sdb, kb);
-    core_vjp(W, sigma_lim, kb, Wb);
+    // core_vjp's forward part depends on W alone: launder W and the accumulated partials so
+    // that it is evaluated here, after the closure reverse, not earlier with its values held
+    T Wl[14];
+#pragma unroll
+    for (int v = 0; v < 14; ++v) {
+      Wl[v] = W[v];
+      opaque(Wl[v]);
+      opaque(Wb[v]);
+    }
+    opaque(kb.rho); opaque(kb.c); opaque(kb.t1); opaque(kb.t2); opaque(kb.sb);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { opaque(kb.Ph[m]); opaque(kb.P2[m]); }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { opaque(kb.qh[i]); opaque(kb.z[i]); }
+    core_vjp(Wl, sigma_lim, kb, Wb);
   }
 
   // flux<d>(W, Qd, Rd, Sd) -> F: reverse
