@@ -5,10 +5,11 @@
 // (Section 3: HLL / Rusanov interface fluxes of MUSCL face states built with the common
 // limiter, BGK source at the cell centre, ghost cells from the boundary conditions).
 // Its reverse runs as deterministic gather passes plus a reduction:
-//   0. prep (adj_prim_kernel, adj_limiter_kernel): primitives of every cell of the domain
-//      and its two ghost layers, and each cell's common limiter factor and the variable that
-//      selected it, per direction (the forward stage's values, bit for bit);
-//   1. faces, per direction (adj_face_kernel, two threads per face, one per face state):
+//   0. prep (adj_prep_kernel, LDS tiles): primitives of every cell of the domain and its two
+//      ghost layers, and each cell's common limiter factor and the variable that selected it,
+//      per direction (the forward stage's values, bit for bit);
+//   1. faces, both directions in one launch (adj_face_kernel, two threads per face, one per
+//      face state):
 //      each thread takes the flux adjoint Fb = (mu_right - mu_left) / dx from the two
 //      adjacent cells (mu = mu_coef dt lam_out, zero in ghost cells), rebuilds its face state
 //      and evaluates its closure (kept for the reverse), wave speeds, flux and conserved
@@ -96,69 +97,107 @@ __device__ __forceinline__ void get_w(const AdjParams& a, long long e, double* W
 }
 
 // ------------------------------------------------------------------ 0. prep
+// Both prep passes in one launch, on tiles of PTX x PTY extended cells: the tile and a ring
+// of one cell recover their primitives into LDS (one conversion per cell and thread in a
+// loop, the ring's cells by the tile's spare threads), then each cell stores its own to wext
+// and forms its limiter factors from its LDS neighbours (the same values as a separate pass
+// over wext, bit for bit).
+template <int DIM> struct PrepTile;
+template <> struct PrepTile<2> { static constexpr int X = 64, Y = 4; };
+template <> struct PrepTile<1> { static constexpr int X = 256, Y = 1; };
+
+template <bool PL> struct PrepSys { using S = Sys14; };
+template <> struct PrepSys<true> { using S = Sys14P; };
+
 template <int DIM, bool PL>
-__global__ __launch_bounds__(ADJ_NT) void adj_prim_kernel(AdjParams a) {
-  const long long e = xcd_block() * ADJ_NT + threadIdx.x;
-  if (e >= a.eplane) return;
-  const int i = (int)(e % a.epitch) - 2;
-  const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
-  if constexpr (PL) {
-    // the planar forward kernel's primitive recovery (the recorded stages ran it)
-    double W[10];
-    load_prims<Sys14P>(a.sp, a.sp.Ub, i, j, W);
+__device__ __forceinline__ void tile_w(const double* sw, int stride, int k, double* W) {
+  using S = typename PrepSys<PL>::S;
 #pragma unroll
-    for (int v = 0; v < 10; ++v) a.wext[Sys14P::plane_of(v) * a.eplane + e] = W[v];
-  } else {
-    double W[14];
-    load_prims<Sys14>(a.sp, a.sp.Ub, i, j, W);
+  for (int v = 0; v < 14; ++v) W[v] = 0.0;
 #pragma unroll
-    for (int v = 0; v < 14; ++v) a.wext[v * a.eplane + e] = W[v];
+  for (int v = 0; v < S::NV; ++v) W[S::plane_of(v)] = sw[v * stride + k];
+}
+
+template <int DIM, int ORDER, bool PL>
+__global__ __launch_bounds__(ADJ_NT) void adj_prep_kernel(AdjParams a) {
+  using S = typename PrepSys<PL>::S;
+  constexpr int NV = S::NV;
+  constexpr int TX = PrepTile<DIM>::X, TY = PrepTile<DIM>::Y;
+  constexpr int R = (ORDER == 2) ? 1 : 0;              // ring of neighbour cells
+  constexpr int HX = TX + 2 * R, HY = (DIM == 2) ? TY + 2 * R : 1;
+  constexpr int HN = HX * HY;
+  __shared__ double sw[NV * HN];
+  const StageParams& p = a.sp;
+  const int eny = (int)(a.eplane / a.epitch);
+  const int ntx = (a.epitch + TX - 1) / TX;
+  const int tile = (int)xcd_block();
+  const int ex0 = (tile % ntx) * TX, ey0 = (tile / ntx) * TY;
+  if (ey0 >= eny) return;                                // uniform per workgroup
+#pragma unroll 1
+  for (int k = threadIdx.x; k < HN; k += ADJ_NT) {
+    const int ex = ex0 - R + k % HX, ey = (DIM == 2) ? ey0 - R + k / HX : 0;
+    double W[NV];
+    if (ex >= 0 && ex < a.epitch && ey >= 0 && ey < eny) {
+      load_prims<S>(p, p.Ub, ex - 2, (DIM == 2) ? ey - 2 : 0, W);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) W[v] = 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sw[v * HN + k] = W[v];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int ex = ex0 + tx, ey = ey0 + ty;
+  if (ex >= a.epitch || ey >= eny) return;
+  const long long e = (long long)ey * a.epitch + ex;
+  const int kc = (ty + ((DIM == 2) ? R : 0)) * HX + tx + R;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a.wext[S::plane_of(v) * a.eplane + e] = sw[v * HN + kc];
+  if constexpr (ORDER == 2) {
+    const int i = ex - 2, j = (DIM == 2) ? ey - 2 : 0;
+    double Wc[14], Wm[14], Wp[14];
+    tile_w<DIM, PL>(sw, HN, kc, Wc);
+    double phi = 0.0;
+    int vs = -1;
+    if (j >= 0 && j < p.ny && i >= -1 && i <= p.nx) {
+      tile_w<DIM, PL>(sw, HN, kc - 1, Wm);
+      tile_w<DIM, PL>(sw, HN, kc + 1, Wp);
+      phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
+    }
+    a.phix[e] = phi;
+    a.vsx[e] = a.frozen_limiter ? -1 : vs;
+    if constexpr (DIM == 2) {
+      phi = 0.0;
+      vs = -1;
+      if (i >= 0 && i < p.nx && j >= -1 && j <= p.ny) {
+        tile_w<DIM, PL>(sw, HN, kc - HX, Wm);
+        tile_w<DIM, PL>(sw, HN, kc + HX, Wp);
+        phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
+      }
+      a.phiy[e] = phi;
+      a.vsy[e] = a.frozen_limiter ? -1 : vs;
+    }
   }
 }
 
-template <int DIM, bool PL>
-__global__ __launch_bounds__(ADJ_NT) void adj_limiter_kernel(AdjParams a) {
-  const StageParams& p = a.sp;
-  const long long e = xcd_block() * ADJ_NT + threadIdx.x;
-  if (e >= a.eplane) return;
-  const int i = (int)(e % a.epitch) - 2;
-  const int j = (DIM == 2) ? (int)(e / a.epitch) - 2 : 0;
-  double Wm[14], Wc[14], Wp[14];
-  double phi = 0.0;
-  int vs = -1;
-  if (j >= 0 && j < p.ny && i >= -1 && i <= p.nx) {
-    get_w<PL>(a, e - 1, Wm);
-    get_w<PL>(a, e, Wc);
-    get_w<PL>(a, e + 1, Wp);
-    phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
-  }
-  a.phix[e] = phi;
-  a.vsx[e] = a.frozen_limiter ? -1 : vs;
-  if constexpr (DIM == 2) {
-    phi = 0.0;
-    vs = -1;
-    if (i >= 0 && i < p.nx && j >= -1 && j <= p.ny) {
-      get_w<PL>(a, e - a.epitch, Wm);
-      get_w<PL>(a, e, Wc);
-      get_w<PL>(a, e + a.epitch, Wp);
-      phi = Adj14::limiter_select(Wm, Wc, Wp, p.limiter, p.fallback, vs);
-    }
-    a.phiy[e] = phi;
-    a.vsy[e] = a.frozen_limiter ? -1 : vs;
-  }
+// workgroups of the prep kernel: one per tile
+template <int DIM>
+static unsigned prep_blocks(const AdjParams& a) {
+  const long long eny = a.eplane / a.epitch;
+  const long long ntx = (a.epitch + PrepTile<DIM>::X - 1) / PrepTile<DIM>::X;
+  const long long nty = (eny + PrepTile<DIM>::Y - 1) / PrepTile<DIM>::Y;
+  return (unsigned)(ntx * nty);
 }
 
 // ------------------------------------------------------------------ 1. faces
+// reverse of face f along D, for its left (right = false) or right state
 template <int D, int DIM, int ORDER, bool PL>
-__global__ __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(PL ? 2 : 1))) void adj_face_kernel(AdjParams a) {
-  // lanes 2k and 2k+1 own the left and the right state of face k; the grid has two threads
-  // per face, so both lanes of a pair pass or fail every face-uniform test together
+__device__ __forceinline__ void face_reverse(const AdjParams& a, long long f, bool right) {
   const StageParams& p = a.sp;
   const int n = (D == 0) ? p.nx : p.ny;           // cells along D
   const int m = (D == 0) ? p.ny : p.nx;           // lines
   const long long nf = (long long)(n + 1) * m;
-  const long long f = (xcd_block() * ADJ_NT + threadIdx.x) >> 1;
-  const bool right = (threadIdx.x & 1) != 0;
   if (f >= nf) return;
   int fc, l;                                       // face fc lies between cells fc-1 and fc
   if (D == 0) { fc = (int)(f % (n + 1)); l = (int)(f / (n + 1)); }
@@ -247,6 +286,22 @@ __global__ __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(PL ? 2 :
 #pragma unroll
   for (int v = 0; v < 14; ++v)
     if (!(PL && zodd(v))) out[v * nf] = Wb[v];
+}
+
+// One launch covers both directions: lanes 2k and 2k+1 own the left and the right state of
+// a face (two threads per face, so both lanes of a pair pass or fail every face-uniform test
+// together); the first bx workgroups take the x faces, the rest the y faces.  One launch
+// instead of one per direction leaves one partly filled last round of wavefronts per stage
+// instead of two.
+template <int DIM, int ORDER, bool PL>
+__global__ __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(PL ? 2 : 1)))
+void adj_face_kernel(AdjParams a) {
+  const long long b = xcd_block();
+  const long long bx = (2 * a.nfx + ADJ_NT - 1) / ADJ_NT;
+  const bool right = (threadIdx.x & 1) != 0;
+  if (DIM == 1 || b < bx) face_reverse<0, DIM, ORDER, PL>(a, (b * ADJ_NT + threadIdx.x) >> 1, right);
+  else if constexpr (DIM == 2)
+    face_reverse<1, DIM, ORDER, PL>(a, ((b - bx) * ADJ_NT + threadIdx.x) >> 1, right);
 }
 
 // ------------------------------------------------------------------ 2. extended cells
@@ -447,7 +502,9 @@ __global__ __launch_bounds__(ADJ_NT) void adj_update_kernel(AdjParams a) {
   if (threadIdx.x < 3) {
     double s = 0.0;
     for (int w = 0; w < ADJ_NT / 64; ++w) s += sRed[threadIdx.x][w];
-    a.part[threadIdx.x * a.n_upd_blocks + blockIdx.x] = s;
+    // each workgroup owns its slot and the stages run in order on one stream: the slot sums
+    // the workgroup's partials over all reverse stages, summed once at the end (fixed order)
+    a.part[threadIdx.x * a.n_upd_blocks + blockIdx.x] += s;
   }
 }
 
@@ -464,7 +521,7 @@ __global__ __launch_bounds__(ADJ_NT) void adj_reduce_kernel(const double* part, 
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int w = 0; w < ADJ_NT / 64; ++w) t += sRed[w];
-      grad[m] += t;
+      grad[m] = t;
     }
     __syncthreads();
   }
@@ -473,13 +530,6 @@ __global__ __launch_bounds__(ADJ_NT) void adj_reduce_kernel(const double* part, 
 // ------------------------------------------------------------------ tape helpers
 __global__ void tape_dt_kernel(const DevCtrl* c, double* slot) {
   if (threadIdx.x == 0) *slot = c->dt;
-}
-
-__global__ void set_dt_kernel(DevCtrl* c, double dt) {
-  if (threadIdx.x == 0) {
-    c->dt = dt;
-    c->status = 0;
-  }
 }
 
 __global__ void pad_copy_kernel(const double* src, double* dst, int nv, int nx, int ny, int pitch,
@@ -504,14 +554,15 @@ int adjoint_update_blocks(int nx, int ny) {
 template <int DIM, int ORDER, bool PL>
 static hipError_t launch_adj_t(AdjParams& a, hipStream_t s) {
   auto blocks = [](long long n) { return dim3((unsigned)((n + ADJ_NT - 1) / ADJ_NT)); };
-  hipLaunchKernelGGL((adj_prim_kernel<DIM, PL>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
-  if constexpr (ORDER == 2)
-    hipLaunchKernelGGL((adj_limiter_kernel<DIM, PL>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
-  hipLaunchKernelGGL((adj_face_kernel<0, DIM, ORDER, PL>), blocks(2 * a.nfx), dim3(ADJ_NT), 0, s, a);
-  if constexpr (DIM == 2)
-    hipLaunchKernelGGL((adj_face_kernel<1, DIM, ORDER, PL>), blocks(2 * a.nfy), dim3(ADJ_NT), 0, s, a);
+  hipLaunchKernelGGL((adj_prep_kernel<DIM, ORDER, PL>), dim3(prep_blocks<DIM>(a)), dim3(ADJ_NT), 0, s, a);
+  const unsigned fblocks = blocks(2 * a.nfx).x + (DIM == 2 ? blocks(2 * a.nfy).x : 0u);
+  hipLaunchKernelGGL((adj_face_kernel<DIM, ORDER, PL>), dim3(fblocks), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL((adj_cell_kernel<DIM, ORDER, PL>), blocks(a.eplane), dim3(ADJ_NT), 0, s, a);
   hipLaunchKernelGGL((adj_update_kernel<DIM, PL>), dim3(a.n_upd_blocks), dim3(ADJ_NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(const AdjParams& a, hipStream_t s) {
   hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(ADJ_NT), 0, s, a.part, a.n_upd_blocks, a.grad);
   return hipGetLastError();
 }
@@ -543,11 +594,6 @@ hipError_t launch_check_planar(const double* f, long long n, DevCtrl* c, hipStre
 
 hipError_t launch_tape_dt(const DevCtrl* c, double* slot, hipStream_t s) {
   hipLaunchKernelGGL(tape_dt_kernel, dim3(1), dim3(64), 0, s, c, slot);
-  return hipGetLastError();
-}
-
-hipError_t launch_set_dt(DevCtrl* c, double dt, hipStream_t s) {
-  hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(64), 0, s, c, dt);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ namespace mx {
 // it needs where it needs them, instead of the compiler sharing them with an earlier forward
 // evaluation (or hoisting them) and keeping them live across the whole reverse.  Compile-time
 // constants (the z-odd zeros of a planar run) are left as they are, so that they still fold.
-template <class T> MX_HD inline void opaque(T& x) {
+template <class T> MX_HD void opaque(T& x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   if (!__builtin_constant_p(x)) asm volatile("" : "+v"(x));
 #else

@@ -7,7 +7,9 @@ namespace mx {
 // Reverse (adjoint) of one stage  Uout = a Ua + beta Ub + mu_coef dt L(Ub)  (14 moments, FP64).
 // Given lam_out (adjoint of Uout) the reverse writes
 //   lam_in = extra_coef lam_extra + beta lam_out + (dL/dUb)^T (mu_coef dt lam_out)
-// and adds the stage's parameter partials (jet Mach, jet density, tau_ref) to grad[3].
+// and adds the stage's parameter partials (jet Mach, jet density, tau_ref), per workgroup of
+// the update kernel, to part (zeroed by the caller before the first reverse stage);
+// launch_adjoint_reduce then sums part into grad[3].
 // The coefficient a of Ua is applied by the caller through the next reverse stage's
 // lam_extra.  All fields are padded SoA like the state.
 struct AdjParams {
@@ -31,9 +33,9 @@ struct AdjParams {
   int* vsx;                  // variable that selected it (-1: a constant factor) [eplane]
   int* vsy;
   int frozen_limiter;        // 1: no derivative through the limiter factors
-  double* part;              // per-workgroup partial sums [3][n_upd_blocks]
+  double* part;              // per-workgroup partial sums over the reverse pass [3][n_upd_blocks]
   int n_upd_blocks;
-  double* grad;              // [3] accumulators: d/d jet Mach, d/d jet rho, d/d tau_ref
+  double* grad;              // [3] sums of part: d/d jet Mach, d/d jet rho, d/d tau_ref
 };
 
 // launchers (mx_adjoint.hip)
@@ -43,9 +45,10 @@ hipError_t launch_adjoint_stage(int dim, int order, bool planar, AdjParams& a, h
 // sets ASYM_Z in ctrl->asym when a z-odd component of the flat 14-moment field f (n cells) is
 // nonzero
 hipError_t launch_check_planar(const double* f, long long n, DevCtrl* c, hipStream_t s);
+// grad[m] = sum over the workgroups of part[m] (fixed order)
+hipError_t launch_adjoint_reduce(const AdjParams& a, hipStream_t s);
 int adjoint_update_blocks(int nx, int ny);
 hipError_t launch_tape_dt(const DevCtrl* c, double* slot, hipStream_t s);
-hipError_t launch_set_dt(DevCtrl* c, double dt, hipStream_t s);
 hipError_t launch_pad_copy(const double* src, double* dst, int nv, int nx, int ny, int pitch,
                            int to_padded, hipStream_t s);
 }  // namespace mx

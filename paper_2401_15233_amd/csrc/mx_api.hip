@@ -852,7 +852,8 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
   if (pl)  // never written in a planar run: they start (and stay) zero
     for (double* l : {lamA, lamB, lamC}) HIP_TRY(s, mx::launch_zero_planes(l, s->plane, 14, s->stream));
   HIP_TRY(s, mx::launch_pad_copy(s->stage, lamA, s->nv, nx, ny, s->pitch, 1, s->stream));
-  HIP_TRY(s, hipMemsetAsync(t->grad, 0, 3 * sizeof(double), s->stream));
+  HIP_TRY(s, hipMemsetAsync(t->part, 0, (size_t)3 * mx::adjoint_update_blocks(nx, ny) * sizeof(double),
+                            s->stream));
 
   mx::AdjParams a;
   std::memset(&a, 0, sizeof(a));
@@ -890,9 +891,9 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
       const bool need_next = j + 1 < m;  // the last step's output is not an input of any stage
       mx::StageParams p = stage_params(s, t->tau[(size_t)(k0 + j)]);
       p.ctrl = t->actrl;
+      p.dt_replay = dtk;   // the recorded dt, passed by value (no control-block update)
       p.do_cfl = 0;
       p.copy_on_idle = 0;
-      HIP_TRY(s, mx::launch_set_dt(t->actrl, dtk, s->stream));
       double* outU = t->seg[(size_t)j];
       if (integ == MAXENT_FE) {
         if (need_next) {
@@ -943,6 +944,7 @@ extern "C" int maxent_step_adjoint(maxent_solver* s, const double* dJ_dU, int dJ
       std::swap(lamA, lamC);
     }
   }
+  HIP_TRY(s, mx::launch_adjoint_reduce(a, s->stream));
   if (dJ_dU0) {
     HIP_TRY(s, mx::launch_pad_copy(lamA, s->stage, s->nv, nx, ny, s->pitch, 0, s->stream));
     HIP_TRY(s, hipMemcpyAsync(dJ_dU0, s->stage, flat,

@@ -40,10 +40,15 @@ __device__ __forceinline__ int jet_on_wall(const StageParams& p, int wall, int s
 }
 
 // Maxwellian inflow state of jet k: density rho_j, temperature T_j, speed M sqrt(5/3 T_j)
-// along the jet angle, P = rho_j T_j I, q = 0, R = 15 p^2 / rho
+// along the jet angle, P = rho_j T_j I, q = 0, R = 15 p^2 / rho (the angle is selected over
+// the four slots, again so that no index into the parameter block is dynamic)
 __device__ __forceinline__ void jet_state(const StageParams& p, int k, double* W) {
+  double ang = p.jet_ang[0];
+#pragma unroll
+  for (int m = 1; m < 4; ++m)
+    if (k == m) ang = p.jet_ang[m];
   double sn, cs;
-  sincospi(p.jet_ang[k] / 180.0, &sn, &cs);
+  sincospi(ang / 180.0, &sn, &cs);
   double spd = p.jet_mach * sqrt(5.0 / 3.0 * p.jet_T);
   double pj = p.jet_rho * p.jet_T;
   W[0] = p.jet_rho;

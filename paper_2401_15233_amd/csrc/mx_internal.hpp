@@ -57,6 +57,7 @@ struct StageParams {
   int copy_on_idle;        // dt == 0: copy Ub to Uout (forward-Euler ping-pong) instead of skipping
   int ntx, nty;            // tile grid
   int nblk;                // real number of tiles
+  double dt_replay;        // > 0: the step's dt (a replayed recorded step); else ctrl->dt
   DevCtrl* ctrl;
 };
 

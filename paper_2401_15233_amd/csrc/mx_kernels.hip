@@ -91,7 +91,7 @@ void stage_kernel(StageParams p) {
   const int j0 = (tile / p.ntx) * TY;
   const int t = threadIdx.x;
 
-  const double dt = p.ctrl->dt;
+  const double dt = p.dt_replay > 0.0 ? p.dt_replay : p.ctrl->dt;
   if (!(dt > 0.0)) {  // uniform: time end reached or a failure stopped the run
     if (p.copy_on_idle && t < TX * TY) {
       int gi = i0 + t % TX, gj = j0 + t / TX;
