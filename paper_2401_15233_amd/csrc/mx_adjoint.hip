@@ -273,6 +273,12 @@ __device__ __forceinline__ void face_reverse(const AdjParams& a, long long f, bo
 #pragma unroll
   for (int v = 0; v < 14; ++v) Wb[v] = 0.0;
   if (any2) {
+    // the wave speeds' reverse first, on the forward's own wave-speed values; the rest reads
+    // laundered inputs (it recomputes what it needs rather than holding the forward's values)
+    Adj14::CoreB<double> kb;
+    Adj14::zero(kb);
+    double udb = 0.0;
+    Adj14::wavespeeds_vjp<D>(k, W[1 + D], p.kws, lminb, lmaxb, kb, udb);
 #pragma unroll
     for (int v = 0; v < 14; ++v) opaque(W[v]);
     opaque_core(k);
@@ -281,7 +287,9 @@ __device__ __forceinline__ void face_reverse(const AdjParams& a, long long f, bo
 #pragma unroll
     for (int i = 0; i < 3; ++i) opaque(Rd[i]);
     opaque(Sd);
-    Adj14::face_terms_vjp_prepared<D>(k, Qd, Rd, Sd, W, p.sigma_lim, p.kws, Ub, Fb, lminb, lmaxb, Wb);
+    Adj14::opaque_b(kb);
+    opaque(udb);
+    Adj14::face_terms_vjp_rest<D>(k, Qd, Rd, Sd, W, p.sigma_lim, Ub, Fb, kb, udb, Wb);
   }
 #pragma unroll
   for (int v = 0; v < 14; ++v)
@@ -292,9 +300,10 @@ __device__ __forceinline__ void face_reverse(const AdjParams& a, long long f, bo
 // a face (two threads per face, so both lanes of a pair pass or fail every face-uniform test
 // together); the first bx workgroups take the x faces, the rest the y faces.  One launch
 // instead of one per direction leaves one partly filled last round of wavefronts per stage
-// instead of two.
+// instead of two.  Two wavefronts per SIMD: the planar kernel fits 256 registers, the full
+// one spills about a hundred (still 13 % faster than one wavefront at 291 registers).
 template <int DIM, int ORDER, bool PL>
-__global__ __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(PL ? 2 : 1)))
+__global__ __launch_bounds__(ADJ_NT) __attribute__((amdgpu_waves_per_eu(2)))
 void adj_face_kernel(AdjParams a) {
   const long long b = xcd_block();
   const long long bx = (2 * a.nfx + ADJ_NT - 1) / ADJ_NT;

@@ -707,14 +707,25 @@ struct Adj14 {
   MX_HD static void face_terms_vjp_prepared(const typename S::template Core<T>& k, const T* Qd,
                                             const T* Rd, T Sd, const T* W, T sigma_lim, T kws,
                                             const T* Ub, const T* Fb, T lminb, T lmaxb, T* Wb) {
+    CoreB<T> kb;
+    zero(kb);
+    T udb = T(0);
+    wavespeeds_vjp<d>(k, W[1 + d], kws, lminb, lmaxb, kb, udb);
+    face_terms_vjp_rest<d>(k, Qd, Rd, Sd, W, sigma_lim, Ub, Fb, kb, udb, Wb);
+  }
+
+  // the same reverse after the wave speeds' (kb and udb: their partials of the core and of
+  // u_d), so that a caller can reverse the wave speeds while their forward values are live
+  template <int d, class T>
+  MX_HD static void face_terms_vjp_rest(const typename S::template Core<T>& k, const T* Qd,
+                                        const T* Rd, T Sd, const T* W, T sigma_lim, const T* Ub,
+                                        const T* Fb, CoreB<T>& kb, T udb, T* Wb) {
     T Qdb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T Rdb[3] = {T(0), T(0), T(0)};
     T Sdb = T(0);
     flux_vjp<d>(W, Qd, Rd, Sd, Fb, Wb, Qdb, Rdb, Sdb);
     prim_to_cons_vjp(W, Ub, Wb);
-    CoreB<T> kb;
-    zero(kb);
-    wavespeeds_vjp<d>(k, W[1 + d], kws, lminb, lmaxb, kb, Wb[1 + d]);
+    Wb[1 + d] += udb;
     closure_dir_vjp<d>(k, Qdb, Rdb, Sdb, kb);
     // core_vjp's forward part depends on W alone: launder W and the accumulated partials so
     // that it is evaluated here, after the closure reverse, not earlier with its values held
@@ -725,12 +736,16 @@ struct Adj14 {
       opaque(Wl[v]);
       opaque(Wb[v]);
     }
+    opaque_b(kb);
+    core_vjp(Wl, sigma_lim, kb, Wb);
+  }
+
+  template <class T> MX_HD static void opaque_b(CoreB<T>& kb) {
     opaque(kb.rho); opaque(kb.c); opaque(kb.t1); opaque(kb.t2); opaque(kb.sb);
 #pragma unroll
     for (int m = 0; m < 6; ++m) { opaque(kb.Ph[m]); opaque(kb.P2[m]); }
 #pragma unroll
     for (int i = 0; i < 3; ++i) { opaque(kb.qh[i]); opaque(kb.z[i]); }
-    core_vjp(Wl, sigma_lim, kb, Wb);
   }
 
   // flux<d>(W, Qd, Rd, Sd) -> F: reverse
