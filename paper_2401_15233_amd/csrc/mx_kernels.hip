@@ -61,14 +61,17 @@ void stage_kernel(StageParams p) {
   constexpr int NFY = (DIM == 2) ? TX * (TY + 1) : 0;
   constexpr int NPX = (ORDER == 2) ? (TX + 2) * TY : 1;
   constexpr int NPY = (ORDER == 2 && DIM == 2) ? TX * (TY + 2) : 1;
-  // planar 2D (XREG): no separate x-flux array (45 KB of LDS per workgroup, three workgroups
-  // per CU).  The x-flux components v >= XK go to LDS at once, past the primitive tile (free
-  // during the face phases); the first XK stay in registers with the y-face fluxes and all of
-  // them overwrite the primitive tile after a barrier
+  // planar 2D (XREG): no separate x-flux array.  The x-flux components v >= XK go to LDS at
+  // once, past the primitive tile (free during the face phases); the first XK stay in
+  // registers through the y-face phase, and all of them overwrite the primitive tile after a
+  // barrier.  XK = 1: the largest LDS footprint that still fits three workgroups per CU
+  // (52 KB each; all ten components would take 54 KB); each component held in registers
+  // instead costs two VGPRs at the kernel's peak, which the three-wavefront build spills
   constexpr bool XREG = (DIM == 2 && NV <= 10);
   constexpr int NFL = XREG ? NV * (NFX + NFY) : NV * NFY;
-  constexpr int NW = (NV * NL > NFL) ? NV * NL : NFL;
-  constexpr int XK = XREG ? NV - (NW - NV * NL) / NFX : NV;
+  constexpr int XK = XREG ? 1 : NV;
+  constexpr int NW0 = XREG ? NV * NL + (NV - XK) * NFX : NV * NL;
+  constexpr int NW = (NW0 > NFL) ? NW0 : NFL;
   constexpr int XH = NW - (NV - XK) * NFX;      // where the LDS-held x-flux components start
   static_assert(!XREG || XH >= NV * NL, "x-flux slots past the primitive tile");
   static_assert(!XREG || XK * NFX + NV * NFY <= XH, "fluxes after the barrier fit below them");
